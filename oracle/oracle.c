@@ -1,0 +1,598 @@
+/*
+ * oracle.c -- plain, slow CPU reference for the per-cell reaction burn.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or constant with
+ * the HIP path: both read the same seeded input arrays and nothing else.
+ *
+ * What it computes (the paper, Sec. 2, "Arbitrary Network Generation": the
+ * network's right-hand side and Jacobian are generated per network, and the
+ * network is integrated with a VODE-class stiff integrator with self-heating;
+ * Sec. 3 uses it cell by cell inside the hydrodynamics).  The paper writes out
+ * neither the rate law nor the integrator, so this file fixes one reading and
+ * states it next to each function:
+ *
+ *   y = (Y_1..Y_N, T),  rho fixed, log-rate multipliers p_r,
+ *   lambda_r(T) = exp(a0 + a1/T + a2 T^-1/3 + a3 T^1/3 + a4 T + a5 T^5/3 + a6 ln T)
+ *   R_r = e^{p_r} lambda_r rho^{n_r - 1} prod_j Y_j^{m_jr} / prod_j m_jr!
+ *   dY_i/dt = sum_r nu_ir R_r,   dT/dt = (1/c_v) sum_r q_r R_r
+ *
+ * and integrates it with a variable-order (1..5) BDF in backward differences
+ * with modified Newton and a dense partially pivoted LU of (I - c J), the
+ * quasi-constant step-size scheme of Shampine & Reichelt (1997) with kappa = 0.
+ *
+ * Parity status: every function below is pinned by a CPU test (closed forms,
+ * invariants, library routines, brute force) except the controller's choice
+ * of step size and order, which has no outside reference: that part is
+ * "parity unpinned" beyond the specification itself.
+ *
+ * Everything is IEEE double; build without fast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_NMAX 64   /* max system size (species + 1) */
+#define ORC_RMAX 512  /* max reactions */
+#define ORC_KMAX 5    /* max BDF order */
+
+/* Per-cell status codes. */
+enum { ORC_OK = 0, ORC_MAX_STEPS = 1, ORC_STEP_UNDERFLOW = 2, ORC_NONFINITE = 3, ORC_BAD_INPUT = 4 };
+/* Per-cell counters. */
+enum { C_STEPS = 0, C_REJ_ERR, C_NEWTON_FAIL, C_RHS, C_JAC, C_LU, C_SOLVE, C_ORDER, C_COUNT };
+
+typedef struct {
+  int n_species, n_reactions;
+  const int32_t *mass;      /* [N] */
+  const int32_t *reactants; /* [R][3], -1 pad, repeats = multiplicity */
+  const int32_t *products;  /* [R][3] */
+  const double *coef;       /* [R][7] */
+  const double *q;          /* [R] */
+  double c_v;
+} orc_net;
+
+typedef struct {
+  double t_end, rtol, atol;
+  int max_steps;
+  /* Test hooks.  fixed_order = 0 runs the scheme as specified.  fixed_order
+   * = k in 1..5 runs k-step BDF at the constant step fixed_h from the history
+   * D_init (k+1 rows of backward differences), with no error test, no order or
+   * step change, and Newton iterated to newton_tol_fixed. */
+  int fixed_order;
+  double fixed_h;
+  const double *D_init;
+  double newton_tol_fixed;
+} orc_opts;
+
+/* ------------------------------------------------------------------------ */
+/* Rates (the ReacLib seven-parameter form)                                  */
+/* ------------------------------------------------------------------------ */
+
+/* lambda_r(T) and d ln lambda_r / dT for every reaction.  mult[r] = e^{p_r}
+ * (or NULL for 1).  The seven basis functions are 1, 1/T, T^-1/3, T^1/3, T,
+ * T^5/3, ln T. */
+void orc_rates(const orc_net *net, double T, const double *log_mult, double *lam,
+               double *dlnlam_dT) {
+  double t13 = cbrt(T);
+  double tm13 = 1.0 / t13;
+  double t53 = T * t13 * t13;
+  double lnT = log(T);
+  double tinv = 1.0 / T;
+  for (int r = 0; r < net->n_reactions; r++) {
+    const double *a = net->coef + 7 * r;
+    double expo = a[0] + a[1] * tinv + a[2] * tm13 + a[3] * t13 + a[4] * T + a[5] * t53 + a[6] * lnT;
+    double l = exp(expo);
+    if (log_mult) l *= exp(log_mult[r]);
+    lam[r] = l;
+    if (dlnlam_dT) {
+      /* d/dT of the exponent, term by term */
+      dlnlam_dT[r] = -a[1] * tinv * tinv
+                     - (1.0 / 3.0) * a[2] * tm13 * tinv
+                     + (1.0 / 3.0) * a[3] * t13 * tinv
+                     + a[4]
+                     + (5.0 / 3.0) * a[5] * t13 * t13
+                     + a[6] * tinv;
+    }
+  }
+}
+
+/* Number of reactant slots in use and 1 / prod(m_j!) for reaction r. */
+static int reaction_order(const orc_net *net, int r, double *inv_fact) {
+  const int32_t *s = net->reactants + 3 * r;
+  int n = 0;
+  for (int i = 0; i < 3; i++) n += (s[i] >= 0);
+  /* multiplicities: count each distinct species */
+  double f = 1.0;
+  for (int i = 0; i < 3; i++) {
+    if (s[i] < 0) continue;
+    int first = 1, m = 0;
+    for (int j = 0; j < i; j++) if (s[j] == s[i]) first = 0;
+    if (!first) continue;
+    for (int j = 0; j < 3; j++) m += (s[j] == s[i]);
+    for (int j = 2; j <= m; j++) f *= (double)j;
+  }
+  *inv_fact = 1.0 / f;
+  return n;
+}
+
+/* Reaction rates R_r at state y = (Y, T). */
+static void reaction_rates(const orc_net *net, double rho, const double *y, const double *log_mult,
+                           double *R, double *lam, double *dlnlam) {
+  int N = net->n_species;
+  orc_rates(net, y[N], log_mult, lam, dlnlam);
+  for (int r = 0; r < net->n_reactions; r++) {
+    double inv_fact;
+    int nr = reaction_order(net, r, &inv_fact);
+    double v = lam[r] * inv_fact;
+    for (int i = 1; i < nr; i++) v *= rho;
+    const int32_t *s = net->reactants + 3 * r;
+    for (int i = 0; i < 3; i++) if (s[i] >= 0) v *= y[s[i]];
+    R[r] = v;
+  }
+}
+
+/* Net stoichiometric coefficient nu_ir (products minus reactants). */
+static int nu(const orc_net *net, int i, int r) {
+  int v = 0;
+  for (int s = 0; s < 3; s++) {
+    v += (net->products[3 * r + s] == i);
+    v -= (net->reactants[3 * r + s] == i);
+  }
+  return v;
+}
+
+/* Right-hand side f(y), n = N+1 entries. */
+void orc_rhs(const orc_net *net, double rho, const double *y, const double *log_mult, double *f) {
+  int N = net->n_species, Rn = net->n_reactions;
+  double R[ORC_RMAX], lam[ORC_RMAX];
+  reaction_rates(net, rho, y, log_mult, R, lam, NULL);
+  for (int i = 0; i < N; i++) {
+    double s = 0.0;
+    for (int r = 0; r < Rn; r++) {
+      int v = nu(net, i, r);
+      if (v) s += (double)v * R[r];
+    }
+    f[i] = s;
+  }
+  double e = 0.0;
+  for (int r = 0; r < Rn; r++) e += net->q[r] * R[r];
+  f[N] = e / net->c_v;
+}
+
+/* Analytic Jacobian J[i*n + j] = d f_i / d y_j (row-major, n = N+1).
+ * dR_r/dY_j: derivative of the slot product, one term per slot holding j,
+ * each term the product of the other slots (so Y_j = 0 is handled).
+ * dR_r/dT = R_r * d ln lambda_r / dT. */
+void orc_jac(const orc_net *net, double rho, const double *y, const double *log_mult, double *J) {
+  int N = net->n_species, Rn = net->n_reactions, n = N + 1;
+  double R[ORC_RMAX], lam[ORC_RMAX], dl[ORC_RMAX];
+  reaction_rates(net, rho, y, log_mult, R, lam, dl);
+  memset(J, 0, sizeof(double) * n * n);
+  for (int r = 0; r < Rn; r++) {
+    double inv_fact;
+    int nr = reaction_order(net, r, &inv_fact);
+    double pre = lam[r] * inv_fact;
+    for (int i = 1; i < nr; i++) pre *= rho;
+    const int32_t *s = net->reactants + 3 * r;
+    /* dR/dY_j for each distinct reactant species j */
+    for (int a = 0; a < 3; a++) {
+      if (s[a] < 0) continue;
+      int j = s[a];
+      double prod = pre;
+      for (int b = 0; b < 3; b++) if (b != a && s[b] >= 0) prod *= y[s[b]];
+      /* this slot's term of dR/dY_j */
+      for (int i = 0; i < N; i++) {
+        int v = nu(net, i, r);
+        if (v) J[i * n + j] += (double)v * prod;
+      }
+      J[N * n + j] += net->q[r] * prod / net->c_v;
+    }
+    double dRdT = R[r] * dl[r];
+    for (int i = 0; i < N; i++) {
+      int v = nu(net, i, r);
+      if (v) J[i * n + N] += (double)v * dRdT;
+    }
+    J[N * n + N] += net->q[r] * dRdT / net->c_v;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU with partial pivoting                                            */
+/* ------------------------------------------------------------------------ */
+
+/* In-place LU of the n x n row-major matrix A with partial pivoting: at column
+ * k the pivot is the first row p >= k with the largest |A[p][k]| (strict >
+ * while scanning down, so ties go to the lowest row); rows k and p are swapped
+ * in full.  piv[k] = p.  Returns 0, or k+1 if the pivot column k is all zero
+ * (singular; A is then partially factored). */
+int orc_lu_factor(int n, double *A, int *piv) {
+  for (int k = 0; k < n; k++) {
+    int p = k;
+    double best = fabs(A[k * n + k]);
+    for (int i = k + 1; i < n; i++) {
+      double v = fabs(A[i * n + k]);
+      if (v > best) { best = v; p = i; }
+    }
+    piv[k] = p;
+    if (!(best > 0.0)) return k + 1;
+    if (p != k) {
+      for (int j = 0; j < n; j++) {
+        double t = A[k * n + j]; A[k * n + j] = A[p * n + j]; A[p * n + j] = t;
+      }
+    }
+    double d = A[k * n + k];
+    for (int i = k + 1; i < n; i++) {
+      double l = A[i * n + k] / d;
+      A[i * n + k] = l;
+      for (int j = k + 1; j < n; j++) A[i * n + j] -= l * A[k * n + j];
+    }
+  }
+  return 0;
+}
+
+/* Solve A x = b with the factors from orc_lu_factor: apply the row swaps in
+ * order, then forward substitution with the unit lower factor, then back
+ * substitution with the upper factor.  b is overwritten with x. */
+void orc_lu_solve(int n, const double *LU, const int *piv, double *b) {
+  for (int k = 0; k < n; k++) {
+    int p = piv[k];
+    if (p != k) { double t = b[k]; b[k] = b[p]; b[p] = t; }
+  }
+  for (int i = 0; i < n; i++) {
+    double s = b[i];
+    for (int j = 0; j < i; j++) s -= LU[i * n + j] * b[j];
+    b[i] = s;
+  }
+  for (int i = n - 1; i >= 0; i--) {
+    double s = b[i];
+    for (int j = i + 1; j < n; j++) s -= LU[i * n + j] * b[j];
+    b[i] = s / LU[i * n + i];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* BDF building blocks                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Weighted RMS norm sqrt((1/n) sum_i (v_i / s_i)^2), summed in ascending i. */
+static double wrms(int n, const double *v, const double *s) {
+  double acc = 0.0;
+  for (int i = 0; i < n; i++) {
+    double z = v[i] / s[i];
+    acc += z * z;
+  }
+  return sqrt(acc / (double)n);
+}
+
+/* gamma_k = sum_{j=1..k} 1/j (gamma_0 = 0). */
+static double bdf_gamma(int k) {
+  double g = 0.0;
+  for (int j = 1; j <= k; j++) g += 1.0 / (double)j;
+  return g;
+}
+
+/* Generalised binomial C(s + j - 1, j) = s (s+1) ... (s+j-1) / j!. */
+static double rising_binom(double s, int j) {
+  double v = 1.0;
+  for (int l = 0; l < j; l++) v *= (s + (double)l) / (double)(l + 1);
+  return v;
+}
+
+/* Change the step size of the backward-difference history by the ratio rho_h.
+ * Rows D_0..D_k hold the backward differences of the degree-k interpolant
+ * p(t_n + s h) = sum_j D_j C(s + j - 1, j).  The new rows are obtained by
+ * evaluating p at the new nodes s = -m rho_h (m = 0..k) and differencing
+ * those values again: D'_a = sum_{m=0..a} (-1)^m C(a, m) p(-m rho_h).
+ * D is stored row-major with n columns. */
+void orc_rescale(int n, int k, double *D, double rho_h) {
+  double v[ORC_KMAX + 1][ORC_NMAX];
+  for (int m = 0; m <= k; m++) {
+    double s = -(double)m * rho_h;
+    for (int i = 0; i < n; i++) {
+      double acc = 0.0;
+      for (int j = 0; j <= k; j++) acc += rising_binom(s, j) * D[j * n + i];
+      v[m][i] = acc;
+    }
+  }
+  for (int a = 0; a <= k; a++) {
+    for (int i = 0; i < n; i++) {
+      double acc = 0.0;
+      double binom = 1.0; /* C(a, m) */
+      for (int m = 0; m <= a; m++) {
+        double sign = (m % 2) ? -1.0 : 1.0;
+        acc += sign * binom * v[m][i];
+        binom = binom * (double)(a - m) / (double)(m + 1);
+      }
+      D[a * n + i] = acc;
+    }
+  }
+}
+
+static int all_finite(int n, const double *v) {
+  for (int i = 0; i < n; i++) if (!isfinite(v[i])) return 0;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One cell                                                                  */
+/* ------------------------------------------------------------------------ */
+
+#define K_MAX 5
+#define SAFETY 0.9
+#define MIN_FACTOR 0.2
+#define MAX_FACTOR 10.0
+#define NEWTON_MAXIT 4
+#define NEWTON_TOL 0.03
+
+/* Integrate one cell from t = 0 to t_end.  y_io holds (Y, T) on entry and
+ * the last accepted state on exit.  cnt receives the eight counters.  Returns
+ * the status code. */
+int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *log_mult,
+                  const orc_opts *o, int32_t *cnt) {
+  const int N = net->n_species, n = N + 1;
+  const double rtol = o->rtol, atol = o->atol, t_end = o->t_end;
+  double D[(K_MAX + 3) * ORC_NMAX];
+  double J[ORC_NMAX * ORC_NMAX], LU[ORC_NMAX * ORC_NMAX];
+  int piv[ORC_NMAX];
+  double y0[ORC_NMAX], f0[ORC_NMAX], f1[ORC_NMAX], s[ORC_NMAX], tmp[ORC_NMAX];
+  double ypred[ORC_NMAX], psi[ORC_NMAX], d[ORC_NMAX], y[ORC_NMAX], F[ORC_NMAX], dy[ORC_NMAX];
+  double s2[ORC_NMAX];
+  for (int c = 0; c < C_COUNT; c++) cnt[c] = 0;
+
+  /* Inputs: rho > 0, T > 0, everything finite. */
+  if (!(rho > 0.0) || !isfinite(rho) || !(y_io[N] > 0.0) || !all_finite(n, y_io)) {
+    return ORC_BAD_INPUT;
+  }
+  memcpy(y0, y_io, sizeof(double) * n);
+
+  int k, n_eq = 0, jac_current, lu_valid = 0;
+  double h, t = 0.0;
+
+  if (o->fixed_order) {
+    k = o->fixed_order;
+    h = o->fixed_h;
+    memset(D, 0, sizeof(D));
+    memcpy(D, o->D_init, sizeof(double) * (k + 1) * n);
+    orc_jac(net, rho, y0, log_mult, J);
+    cnt[C_JAC]++;
+    jac_current = 1;
+  } else {
+    /* Initial step (Hairer, Norsett & Wanner, vol. I, Sec. II.4, order 1). */
+    orc_rhs(net, rho, y0, log_mult, f0);
+    cnt[C_RHS]++;
+    if (!all_finite(n, f0)) return ORC_NONFINITE;
+    for (int i = 0; i < n; i++) s[i] = atol + rtol * fabs(y0[i]);
+    double d0 = wrms(n, y0, s), d1 = wrms(n, f0, s);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    if (h0 > t_end) h0 = t_end;
+    for (int i = 0; i < n; i++) tmp[i] = y0[i] + h0 * f0[i];
+    orc_rhs(net, rho, tmp, log_mult, f1);
+    cnt[C_RHS]++;
+    for (int i = 0; i < n; i++) tmp[i] = f1[i] - f0[i];
+    double d2 = wrms(n, tmp, s) / h0;
+    double h1;
+    if (!isfinite(d2)) {
+      h1 = 1e-3 * h0;
+    } else {
+      double dm = d1 > d2 ? d1 : d2;
+      if (dm <= 1e-15) {
+        h1 = 1e-3 * h0;
+        if (h1 < 1e-6) h1 = 1e-6;
+      } else {
+        h1 = sqrt(0.01 / dm);
+      }
+    }
+    h = 100.0 * h0;
+    if (h1 < h) h = h1;
+    if (t_end < h) h = t_end;
+
+    /* History: D_0 = y0, D_1 = h f0, the rest zero; order 1. */
+    k = 1;
+    memset(D, 0, sizeof(D));
+    for (int i = 0; i < n; i++) { D[i] = y0[i]; D[n + i] = h * f0[i]; }
+    orc_jac(net, rho, y0, log_mult, J);
+    cnt[C_JAC]++;
+    if (!all_finite(n * n, J)) return ORC_NONFINITE;
+    jac_current = 1;
+  }
+
+  int status = ORC_OK;
+  double err = 0.0;
+  while (t < t_end) {
+    if (cnt[C_STEPS] >= o->max_steps) { status = ORC_MAX_STEPS; break; }
+    /* ---- one accepted step (with rejections and retries) ---- */
+    int accepted = 0;
+    double t_new = t;
+    while (!accepted) {
+      /* Step underflow: h below ten units in the last place of t. */
+      double ulp = nextafter(t, INFINITY) - t;
+      if (h < 10.0 * ulp) { status = ORC_STEP_UNDERFLOW; break; }
+      /* Land exactly on t_end. */
+      t_new = t + h;
+      if (t_new > t_end) {
+        t_new = t_end;
+        orc_rescale(n, k, D, (t_end - t) / h);
+        h = t_end - t;
+        n_eq = 0;
+        lu_valid = 0;
+      }
+      /* Predictor, psi, Newton scale, c = h / gamma_k. */
+      double gk = bdf_gamma(k);
+      for (int i = 0; i < n; i++) {
+        double a = 0.0;
+        for (int j = 0; j <= k; j++) a += D[j * n + i];
+        ypred[i] = a;
+        double b = 0.0;
+        for (int j = 1; j <= k; j++) b += bdf_gamma(j) * D[j * n + i];
+        psi[i] = b / gk;
+        s[i] = atol + rtol * fabs(ypred[i]);
+      }
+      double cc = h / gk;
+
+      /* Modified Newton; on failure refresh a stale Jacobian once. */
+      int converged = 0;
+      for (;;) {
+        int singular = 0;
+        if (!lu_valid) {
+          for (int i = 0; i < n; i++)
+            for (int j = 0; j < n; j++) LU[i * n + j] = (i == j ? 1.0 : 0.0) - cc * J[i * n + j];
+          singular = orc_lu_factor(n, LU, piv);
+          cnt[C_LU]++;
+          lu_valid = 1;
+        }
+        if (!singular) {
+          double tol = o->fixed_order ? o->newton_tol_fixed : NEWTON_TOL;
+          int maxit = o->fixed_order ? 50 : NEWTON_MAXIT;
+          double dprev = 0.0;
+          for (int i = 0; i < n; i++) { d[i] = 0.0; y[i] = ypred[i]; }
+          for (int it = 0; it < maxit; it++) {
+            orc_rhs(net, rho, y, log_mult, F);
+            cnt[C_RHS]++;
+            if (!all_finite(n, F)) break;
+            for (int i = 0; i < n; i++) dy[i] = cc * F[i] - psi[i] - d[i];
+            orc_lu_solve(n, LU, piv, dy);
+            cnt[C_SOLVE]++;
+            double dn = wrms(n, dy, s);
+            if (!isfinite(dn)) break;
+            double rate = 0.0;
+            if (it > 0) {
+              rate = dn / dprev;
+              if (rate >= 1.0 || pow(rate, (double)(maxit - it)) / (1.0 - rate) * dn > tol) break;
+            }
+            for (int i = 0; i < n; i++) { y[i] += dy[i]; d[i] += dy[i]; }
+            if (dn == 0.0 || (it > 0 && rate / (1.0 - rate) * dn < tol)) { converged = 1; break; }
+            dprev = dn;
+          }
+        }
+        /* A singular Newton matrix counts as a failed Newton attempt. */
+        if (converged) break;
+        cnt[C_NEWTON_FAIL]++;
+        if (jac_current) break;
+        orc_jac(net, rho, ypred, log_mult, J);
+        cnt[C_JAC]++;
+        jac_current = 1;
+        lu_valid = 0;
+      }
+      if (!converged) {
+        if (o->fixed_order) { status = ORC_STEP_UNDERFLOW; break; }
+        /* Halve the step and retry. */
+        h *= 0.5;
+        orc_rescale(n, k, D, 0.5);
+        n_eq = 0;
+        lu_valid = 0;
+        continue;
+      }
+
+      /* Error test with scale atol + rtol * max(|y_n|, |y_new|). */
+      for (int i = 0; i < n; i++) {
+        double a = fabs(D[i]), b = fabs(y[i]);
+        s2[i] = atol + rtol * (a > b ? a : b);
+        tmp[i] = d[i] / (double)(k + 1);
+      }
+      err = wrms(n, tmp, s2);
+      if (!o->fixed_order && err > 1.0) {
+        double factor = SAFETY * pow(err, -1.0 / (double)(k + 1));
+        if (factor < MIN_FACTOR) factor = MIN_FACTOR;
+        h *= factor;
+        orc_rescale(n, k, D, factor);
+        n_eq = 0;
+        lu_valid = 0;
+        cnt[C_REJ_ERR]++;
+        continue;
+      }
+      accepted = 1;
+    }
+    if (!accepted) break;
+
+    /* Accept: update the differences. */
+    t = t_new;
+    for (int i = 0; i < n; i++) {
+      D[(k + 2) * n + i] = d[i] - D[(k + 1) * n + i];
+      D[(k + 1) * n + i] = d[i];
+    }
+    for (int j = k; j >= 0; j--)
+      for (int i = 0; i < n; i++) D[j * n + i] += D[(j + 1) * n + i];
+    jac_current = 0;
+    n_eq++;
+    cnt[C_STEPS]++;
+    if (o->fixed_order) continue;
+
+    /* Order and step-size selection after k+1 steps at constant h. */
+    if (n_eq >= k + 1) {
+      double em = INFINITY, ep = INFINITY;
+      if (k > 1) {
+        for (int i = 0; i < n; i++) tmp[i] = D[k * n + i] / (double)k;
+        em = wrms(n, tmp, s2);
+      }
+      if (k < K_MAX) {
+        for (int i = 0; i < n; i++) tmp[i] = D[(k + 2) * n + i] / (double)(k + 2);
+        ep = wrms(n, tmp, s2);
+      }
+      double fm = pow(em, -1.0 / (double)k);
+      double f0_ = pow(err, -1.0 / (double)(k + 1));
+      double fp = pow(ep, -1.0 / (double)(k + 2));
+      double best = f0_;
+      int dk = 0;
+      if (fm > best) { best = fm; dk = -1; }
+      if (fp > best) { best = fp; dk = 1; }
+      k += dk;
+      double factor = SAFETY * best;
+      if (factor > MAX_FACTOR) factor = MAX_FACTOR;
+      h *= factor;
+      orc_rescale(n, k, D, factor);
+      n_eq = 0;
+      lu_valid = 0;
+    }
+  }
+  cnt[C_ORDER] = k;
+  memcpy(y_io, D, sizeof(double) * n);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batch driver (structure-of-arrays, like the GPU boundary)                 */
+/* ------------------------------------------------------------------------ */
+
+/* Burn n_cells independent cells.  Y is [N][C] (in/out), T is [C] (in/out),
+ * rho is [C]; status [C] and counters [8][C] are outputs (either may be NULL).
+ * n_threads <= 0 uses the OpenMP default.  Returns 0, or -1 on bad sizes. */
+int orc_burn_batch(const orc_net *net, int64_t n_cells, double *Y, const double *rho, double *T,
+                   const double *log_mult, const orc_opts *o, int32_t *status, int32_t *counters,
+                   int n_threads) {
+  int N = net->n_species;
+  if (N < 1 || N + 1 > ORC_NMAX || net->n_reactions < 1 || net->n_reactions > ORC_RMAX ||
+      n_cells < 0)
+    return -1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t c = 0; c < n_cells; c++) {
+    double y[ORC_NMAX];
+    int32_t cnt[C_COUNT];
+    for (int i = 0; i < N; i++) y[i] = Y[(int64_t)i * n_cells + c];
+    y[N] = T[c];
+    int st = orc_burn_cell(net, rho[c], y, log_mult, o, cnt);
+    for (int i = 0; i < N; i++) Y[(int64_t)i * n_cells + c] = y[i];
+    T[c] = y[N];
+    if (status) status[c] = st;
+    if (counters)
+      for (int j = 0; j < C_COUNT; j++) counters[(int64_t)j * n_cells + c] = cnt[j];
+  }
+  return 0;
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

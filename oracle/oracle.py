@@ -1,0 +1,212 @@
+"""ctypes binding of the plain C oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product package.
+
+``build()`` compiles oracle.c with gcc (-O2, no fast-math, no FMA
+contraction, OpenMP) into liboracle.so next to this file.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+STATUS = {0: "OK", 1: "MAX_STEPS", 2: "STEP_UNDERFLOW", 3: "NONFINITE", 4: "BAD_INPUT"}
+COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "n_solve", "order"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so (always when force)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-Wno-unused-variable", SRC, "-o", LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Net(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("n_reactions", C.c_int),
+                ("mass", C.POINTER(C.c_int32)), ("reactants", C.POINTER(C.c_int32)),
+                ("products", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double)), ("c_v", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("t_end", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+                ("max_steps", C.c_int), ("fixed_order", C.c_int), ("fixed_h", C.c_double),
+                ("D_init", C.POINTER(C.c_double)), ("newton_tol_fixed", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+        L.orc_rates.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
+        L.orc_rhs.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
+        L.orc_jac.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
+        L.orc_lu_factor.argtypes = [C.c_int, dp, ip]
+        L.orc_lu_factor.restype = C.c_int
+        L.orc_lu_solve.argtypes = [C.c_int, dp, ip, dp]
+        L.orc_rescale.argtypes = [C.c_int, C.c_int, dp, C.c_double]
+        L.orc_burn_cell.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, C.POINTER(_Opts),
+                                    C.POINTER(C.c_int32)]
+        L.orc_burn_cell.restype = C.c_int
+        L.orc_burn_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, C.POINTER(_Opts),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int]
+        L.orc_burn_batch.restype = C.c_int
+        L.orc_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class OracleNet:
+    """Holds the network arrays alive and the C struct pointing at them."""
+
+    def __init__(self, spec):
+        spec.validate()
+        self.spec = spec
+        self.mass = np.ascontiguousarray(spec.mass, dtype=np.int32)
+        self.reactants = np.ascontiguousarray(spec.reactants, dtype=np.int32)
+        self.products = np.ascontiguousarray(spec.products, dtype=np.int32)
+        self.coef = np.ascontiguousarray(spec.coef, dtype=np.float64)
+        self.q = np.ascontiguousarray(spec.q, dtype=np.float64)
+        i32 = C.POINTER(C.c_int32)
+        self.c = _Net(spec.n_species, spec.n_reactions, self.mass.ctypes.data_as(i32),
+                      self.reactants.ctypes.data_as(i32), self.products.ctypes.data_as(i32),
+                      _dp(self.coef), _dp(self.q), float(spec.c_v))
+        self.N = spec.n_species
+        self.R = spec.n_reactions
+        self.n = self.N + 1
+
+
+def _lm(net: OracleNet, log_mult) -> Optional[np.ndarray]:
+    if log_mult is None:
+        return None
+    lm = np.ascontiguousarray(log_mult, dtype=np.float64)
+    assert lm.shape == (net.R,)
+    return lm
+
+
+def rates(net: OracleNet, T: float, log_mult=None) -> Tuple[np.ndarray, np.ndarray]:
+    lam = np.zeros(net.R)
+    dl = np.zeros(net.R)
+    lm = _lm(net, log_mult)
+    lib().orc_rates(C.byref(net.c), float(T), _dp(lm), _dp(lam), _dp(dl))
+    return lam, dl
+
+
+def rhs(net: OracleNet, rho: float, y, log_mult=None) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    f = np.zeros(net.n)
+    lm = _lm(net, log_mult)
+    lib().orc_rhs(C.byref(net.c), float(rho), _dp(y), _dp(lm), _dp(f))
+    return f
+
+
+def jac(net: OracleNet, rho: float, y, log_mult=None) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    J = np.zeros((net.n, net.n))
+    lm = _lm(net, log_mult)
+    lib().orc_jac(C.byref(net.c), float(rho), _dp(y), _dp(lm), _dp(J))
+    return J
+
+
+def lu_factor(A) -> Tuple[np.ndarray, np.ndarray, int]:
+    A = np.array(A, dtype=np.float64, order="C", copy=True)
+    n = A.shape[0]
+    piv = np.zeros(n, dtype=np.intc)
+    info = lib().orc_lu_factor(n, _dp(A), piv.ctypes.data_as(C.POINTER(C.c_int)))
+    return A, piv, int(info)
+
+
+def lu_solve(LU, piv, b) -> np.ndarray:
+    x = np.array(b, dtype=np.float64, copy=True)
+    LU = np.ascontiguousarray(LU, dtype=np.float64)
+    piv = np.ascontiguousarray(piv, dtype=np.intc)
+    lib().orc_lu_solve(LU.shape[0], _dp(LU), piv.ctypes.data_as(C.POINTER(C.c_int)), _dp(x))
+    return x
+
+
+def rescale(D, k: int, rho_h: float) -> np.ndarray:
+    """D: [rows >= k+1, n] backward differences; returns a rescaled copy."""
+    D = np.array(D, dtype=np.float64, order="C", copy=True)
+    lib().orc_rescale(D.shape[1], int(k), _dp(D), float(rho_h))
+    return D
+
+
+def _opts(t_end, rtol, atol, max_steps, fixed_order=0, fixed_h=0.0, D_init=None, tol=1e-12):
+    return _Opts(float(t_end), float(rtol), float(atol), int(max_steps), int(fixed_order),
+                 float(fixed_h), _dp(D_init), float(tol))
+
+
+def burn_cell(net: OracleNet, rho: float, y0, t_end: float, rtol: float = 1e-6,
+              atol: float = 1e-10, log_mult=None, max_steps: int = 100000):
+    """One cell; returns (y_end, status, counters[8])."""
+    y = np.array(y0, dtype=np.float64, copy=True)
+    cnt = np.zeros(8, dtype=np.int32)
+    lm = _lm(net, log_mult)
+    o = _opts(t_end, rtol, atol, max_steps)
+    st = lib().orc_burn_cell(C.byref(net.c), float(rho), _dp(y), _dp(lm), C.byref(o),
+                             cnt.ctypes.data_as(C.POINTER(C.c_int32)))
+    return y, int(st), cnt
+
+
+def burn_fixed(net: OracleNet, rho: float, D_init, k: int, h: float, n_steps: int,
+               log_mult=None, newton_tol: float = 1e-12):
+    """Test hook: k-step BDF at constant h from the given backward
+    differences (k+1 rows), n_steps steps, Newton iterated to newton_tol.
+    Returns (y_end, status, counters)."""
+    D_init = np.ascontiguousarray(D_init, dtype=np.float64)
+    assert D_init.shape == (k + 1, net.n)
+    y = np.array(D_init[0], copy=True)
+    cnt = np.zeros(8, dtype=np.int32)
+    lm = _lm(net, log_mult)
+    o = _opts(1e300, 1e-6, 1e-10, n_steps, k, h, D_init, newton_tol)
+    st = lib().orc_burn_cell(C.byref(net.c), float(rho), _dp(y), _dp(lm), C.byref(o),
+                             cnt.ctypes.data_as(C.POINTER(C.c_int32)))
+    return y, int(st), cnt
+
+
+def burn(net: OracleNet, cells, t_end: float, rtol: float = 1e-6, atol: float = 1e-10,
+         log_mult=None, max_steps: int = 100000, n_threads: int = 0):
+    """Batch burn on the host.  cells: synth.Cells.  Returns
+    (Y[N,C], T[C], status[C], counters[8,C])."""
+    Y = np.array(cells.Y, dtype=np.float64, order="C", copy=True)
+    T = np.array(cells.T, dtype=np.float64, copy=True)
+    rho = np.ascontiguousarray(cells.rho, dtype=np.float64)
+    C_ = rho.shape[0]
+    st = np.zeros(C_, dtype=np.int32)
+    cnt = np.zeros((8, C_), dtype=np.int32)
+    lm = _lm(net, log_mult)
+    o = _opts(t_end, rtol, atol, max_steps)
+    rc = lib().orc_burn_batch(C.byref(net.c), C_, _dp(Y), _dp(rho), _dp(T), _dp(lm), C.byref(o),
+                              st.ctypes.data_as(C.POINTER(C.c_int32)),
+                              cnt.ctypes.data_as(C.POINTER(C.c_int32)), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the network size")
+    return Y, T, st, cnt
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
