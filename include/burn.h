@@ -1,0 +1,143 @@
+/*
+ * burn.h -- C ABI of the MI355X per-cell reaction-network burn (libburn.so).
+ *
+ * The operation: every cell is an independent zone at fixed density rho that
+ * evolves its molar abundances Y_1..Y_N and temperature T over a time dt
+ * (the single-zone burn with self-heating of the paper, Sec. 2, where the
+ * generated network RHS and Jacobian are integrated with a VODE-class stiff
+ * integrator; Sec. 3 applies it zone by zone inside the hydrodynamics).
+ *
+ *   dY_i/dt = sum_r nu_ir R_r,          dT/dt = (1/c_v) sum_r q_r R_r,
+ *   R_r     = e^{p_r} lambda_r(T) rho^{n_r-1} prod_j Y_j^{m_jr} / prod_j m_jr!,
+ *   lambda_r(T) = exp(a0 + a1/T + a2 T^-1/3 + a3 T^1/3 + a4 T + a5 T^5/3 + a6 ln T)
+ *
+ * (the seven-parameter ReacLib rate form; the rate collections themselves are
+ * cited in Sec. 2).  nu_ir = products minus reactants multiplicity, m_jr =
+ * reactant multiplicity, n_r = number of reactant slots, p_r = log-rate
+ * multiplier (the sensitivity knob of Sec. 1).  The integrator is a
+ * variable-order (1..5) BDF in backward differences with modified Newton and
+ * a dense partially pivoted LU of (I - c J), all in FP64.
+ *
+ * Conventions for every entry point:
+ *  - Arrays marked DEVICE are device pointers (memory owned by the caller,
+ *    e.g. PyTorch); arrays marked HOST are host pointers.
+ *  - Cell arrays are structure-of-arrays: element (i, c) of a [K][n_cells]
+ *    array is at i * n_cells + c, so consecutive cells are consecutive.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *    asynchronously; outputs are valid after the stream is synchronized.
+ *  - A negative return value means nothing was enqueued; bn_last_error()
+ *    then describes why.  Per-cell outcomes go to status[] (BN_CELL_*).
+ *  - The library keeps no pointer to caller memory after the enqueued work
+ *    finishes.  A network handle owns a small device copy of its tables.
+ */
+#ifndef MI355X_BURN_H
+#define MI355X_BURN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Call-level return codes. */
+#define BN_SUCCESS 0
+#define BN_EINVAL (-1)       /* null pointer, bad size, rtol <= 0, atol < 0, dt <= 0, ... */
+#define BN_EHIP (-2)         /* a HIP runtime call failed */
+#define BN_ENOMEM (-3)       /* device allocation failed */
+#define BN_EUNSUPPORTED (-4) /* network larger than the kernels support */
+
+/* Per-cell outcomes written to status[]. */
+#define BN_CELL_OK 0             /* reached dt */
+#define BN_CELL_MAX_STEPS 1      /* step budget exhausted */
+#define BN_CELL_STEP_UNDERFLOW 2 /* step fell below 10 ulp(t) */
+#define BN_CELL_NONFINITE 3      /* rates / RHS / Jacobian not finite at the initial state */
+#define BN_CELL_BAD_INPUT 4      /* rho <= 0, T <= 0, or a non-finite input */
+
+/* Per-cell counters written to counters[BN_N_COUNTERS][n_cells]. */
+#define BN_N_COUNTERS 8
+#define BN_CNT_STEPS 0       /* accepted steps */
+#define BN_CNT_REJ_ERR 1     /* error-test rejections */
+#define BN_CNT_NEWTON_FAIL 2 /* failed Newton attempts */
+#define BN_CNT_RHS 3         /* right-hand-side evaluations */
+#define BN_CNT_JAC 4         /* Jacobian evaluations */
+#define BN_CNT_LU 5          /* LU factorizations of I - cJ */
+#define BN_CNT_SOLVE 6       /* forward/back substitution pairs */
+#define BN_CNT_ORDER 7       /* BDF order at the end */
+
+/* Largest supported system: species + temperature. */
+#define BN_MAX_SYSTEM 64
+#define BN_MAX_REACTIONS 1024
+
+typedef struct bn_network bn_network; /* opaque, immutable after create */
+
+/* Network description (all HOST pointers, read during bn_network_create). */
+typedef struct {
+  int32_t n_species;        /* N >= 1, N + 1 <= BN_MAX_SYSTEM */
+  int32_t n_reactions;      /* R >= 1, R <= BN_MAX_REACTIONS */
+  const int32_t *mass;      /* [N] mass numbers A_i >= 1 */
+  const int32_t *reactants; /* [R][3] species index per slot, -1 = empty;
+                               a repeated index is a multiplicity (2B = B,B,-1);
+                               at least one slot in use */
+  const int32_t *products;  /* [R][3] same convention (may be all -1) */
+  const double *coef;       /* [R][7] a0..a6 of the rate fit */
+  const double *q;          /* [R] heat released per reaction event */
+  double c_v;               /* specific heat, > 0 */
+} bn_network_desc;
+
+/* Validate `desc` (indices in range, every reaction conserves mass number,
+ * finite coefficients, c_v > 0), build the device tables and return a handle
+ * in *out.  Returns BN_SUCCESS, BN_EINVAL, BN_EUNSUPPORTED, BN_ENOMEM or
+ * BN_EHIP.  The handle is bound to the device current at creation. */
+int bn_network_create(const bn_network_desc *desc, bn_network **out);
+
+/* Free the handle and its device tables (NULL is a no-op).  The caller must
+ * make sure no enqueued burn still uses it. */
+void bn_network_destroy(bn_network *net);
+
+/* Number of species / reactions of a handle (-1 for NULL). */
+int bn_network_n_species(const bn_network *net);
+int bn_network_n_reactions(const bn_network *net);
+
+/* Burn n_cells independent cells from t = 0 to t = dt.
+ *   state    DEVICE [N][n_cells]  molar abundances Y, in/out
+ *   rho      DEVICE [n_cells]     density (> 0)
+ *   T        DEVICE [n_cells]     temperature (> 0), in/out
+ *   dt > 0, rtol > 0, atol >= 0   end time and tolerances (atol applies to
+ *                                 every component, temperature included)
+ *   log_mult DEVICE [R] or NULL   p_r: lambda_r is multiplied by exp(p_r)
+ *   status   DEVICE [n_cells] or NULL              BN_CELL_* per cell
+ *   counters DEVICE [BN_N_COUNTERS][n_cells] or NULL
+ *   stream   hipStream_t or NULL
+ * A cell that fails keeps its last accepted (Y, T); a BAD_INPUT or
+ * NONFINITE cell is left unchanged.  n_cells == 0 is a no-op.
+ * Returns BN_SUCCESS or a negative code (nothing enqueued). */
+int burn_batch(const bn_network *net, int64_t n_cells, double *state, const double *rho,
+               double *T, double dt, double rtol, double atol, const double *log_mult,
+               int32_t *status, int32_t *counters, void *stream);
+
+/* Optional knobs for burn_batch_ex (zero-initialise, then set fields). */
+typedef struct {
+  int32_t max_steps;      /* accepted-step budget per cell; <= 0 means 100000 */
+  int32_t lanes_per_cell; /* 0 = automatic; otherwise 4, 8, 16 or 64 (tuning) */
+  int32_t block_waves;    /* 0 = automatic; waves per workgroup (tuning) */
+  int32_t reserved;
+} bn_burn_opts;
+
+/* burn_batch with knobs (opts may be NULL: defaults). */
+int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const double *rho,
+                  double *T, double dt, double rtol, double atol, const double *log_mult,
+                  int32_t *status, int32_t *counters, const bn_burn_opts *opts, void *stream);
+
+/* Thread-local description of the last failed call on this thread ("" if
+ * none); valid until the next call from the same thread. */
+const char *bn_last_error(void);
+
+/* Library version string. */
+const char *bn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355X_BURN_H */

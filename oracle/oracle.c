@@ -409,9 +409,10 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
     int accepted = 0;
     double t_new = t;
     while (!accepted) {
-      /* Step underflow: h below ten units in the last place of t. */
+      /* Step underflow: h below ten units in the last place of t (a
+       * non-finite h counts too, so every cell terminates). */
       double ulp = nextafter(t, INFINITY) - t;
-      if (h < 10.0 * ulp) { status = ORC_STEP_UNDERFLOW; break; }
+      if (!(h >= 10.0 * ulp)) { status = ORC_STEP_UNDERFLOW; break; }
       /* Land exactly on t_end. */
       t_new = t + h;
       if (t_new > t_end) {

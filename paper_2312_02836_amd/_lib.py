@@ -1,0 +1,74 @@
+"""ctypes loader for libburn.so (argument marshalling only).
+
+PyTorch is imported first so that libburn.so binds to the HIP runtime torch
+already loaded (one runtime per process).  There is no fallback: if the
+library is missing the import of the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (must precede the library load: shared HIP runtime)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libburn.so")
+
+BN_SUCCESS, BN_EINVAL, BN_EHIP, BN_ENOMEM, BN_EUNSUPPORTED = 0, -1, -2, -3, -4
+CELL_STATUS = {0: "OK", 1: "MAX_STEPS", 2: "STEP_UNDERFLOW", 3: "NONFINITE", 4: "BAD_INPUT"}
+COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "n_solve", "order"]
+
+# Every symbol include/burn.h declares.
+EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
+           "bn_network_n_reactions", "burn_batch", "burn_batch_ex", "bn_last_error", "bn_version"]
+
+
+class NetworkDesc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
+                ("mass", C.POINTER(C.c_int32)), ("reactants", C.POINTER(C.c_int32)),
+                ("products", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_double)),
+                ("q", C.POINTER(C.c_double)), ("c_v", C.c_double)]
+
+
+class BurnOpts(C.Structure):
+    _fields_ = [("max_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
+                ("block_waves", C.c_int32), ("reserved", C.c_int32)]
+
+
+class BurnError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BurnError(f"{LIB_PATH} is not built (python -m paper_2312_02836_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.c_void_p, C.c_void_p
+    L.bn_network_create.argtypes = [C.POINTER(NetworkDesc), C.POINTER(C.c_void_p)]
+    L.bn_network_create.restype = C.c_int
+    L.bn_network_destroy.argtypes = [vp]
+    L.bn_network_destroy.restype = None
+    L.bn_network_n_species.argtypes = [vp]
+    L.bn_network_n_reactions.argtypes = [vp]
+    L.burn_batch.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp,
+                             ip, ip, vp]
+    L.burn_batch.restype = C.c_int
+    L.burn_batch_ex.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                dp, ip, ip, C.POINTER(BurnOpts), vp]
+    L.burn_batch_ex.restype = C.c_int
+    L.bn_last_error.restype = C.c_char_p
+    L.bn_version.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str) -> None:
+    if rc != BN_SUCCESS:
+        msg = lib().bn_last_error().decode()
+        raise BurnError(f"{what} failed ({rc}): {msg}")

@@ -1,0 +1,65 @@
+"""Algorithmic FP64 operation count of a burn, from the per-cell counters.
+
+Every operation the method must perform is counted once: add, mul, fma (2),
+division, square root and each transcendental (exp, log, cbrt, pow) as one
+operation, whatever its cost in instructions on a given chip.  The terms:
+
+  F_rhs    T powers (6) + per reaction r: exponent (12) + exp + multiplier +
+           1/prod(m!) + rho^(n_r-1) + the n_r abundance factors + heat (2),
+           + 2 per nonzero stoichiometric entry + 1 for the temperature row
+  F_jac    rates with d ln(lambda)/dT, the slot-product derivatives of every
+           (row, reaction) pair and the temperature row
+  F_lu     I - cJ (2 n^2) + partial-pivot LU: n reciprocals + n(n-1)/2
+           multipliers + n(n-1)(2n-1)/3 for the trailing updates
+  F_solve  forward + back substitution (2 n^2 - n) + the Newton vector work
+           (8 n + 3: right side, weighted norm, updates)
+  F_att    per step attempt: predictor, psi, scales and error test at the
+           highest order ((3*5 + 13) n)
+  F_acc    per accepted step: history update and order-choice norms (14 n)
+  F_resc   per step-size change: the (k+1)^2 history transform at k = 5
+           (132 n); the number of changes is estimated as n_lu - n_jac
+
+F_cell = n_rhs F_rhs + n_jac F_jac + n_lu F_lu + n_solve F_solve
+         + (n_steps + n_rej + n_fail) F_att + n_steps F_acc + n_resc F_resc
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def per_eval_costs(spec) -> dict:
+    n = spec.n
+    nr = (spec.reactants >= 0).sum(axis=1).astype(np.int64)
+    nu_nz = []
+    for r in range(spec.n_reactions):
+        v = {}
+        for s in spec.reactants[r]:
+            if s >= 0:
+                v[int(s)] = v.get(int(s), 0) - 1
+        for s in spec.products[r]:
+            if s >= 0:
+                v[int(s)] = v.get(int(s), 0) + 1
+        nu_nz.append(sum(1 for x in v.values() if x))
+    nu_nz = np.array(nu_nz, dtype=np.int64)
+    nnz = int(nu_nz.sum())
+    f_rhs = 7 + int((17 + 2 * nr).sum()) + 2 * nnz
+    f_jac = 6 + int((34 + 2 * nr).sum()) + int((nu_nz * (nr * (nr + 1) + 2)).sum()) + int(
+        (nr * (nr + 2) + 3).sum())
+    f_lu = 2 * n * n + n + n * (n - 1) // 2 + n * (n - 1) * (2 * n - 1) // 3
+    f_solve = 2 * n * n - n + 8 * n + 3
+    return {"rhs": f_rhs, "jac": f_jac, "lu": f_lu, "solve": f_solve, "att": 28 * n,
+            "acc": 14 * n, "resc": 132 * n}
+
+
+def cell_flops(spec, counters: np.ndarray) -> np.ndarray:
+    """Per-cell algorithmic operation count; counters is [8, C]."""
+    c = np.asarray(counters, dtype=np.int64)
+    n_steps, n_rej, n_fail, n_rhs, n_jac, n_lu, n_solve = c[:7]
+    k = per_eval_costs(spec)
+    n_resc = np.maximum(n_lu - n_jac, 0)
+    return (n_rhs * k["rhs"] + n_jac * k["jac"] + n_lu * k["lu"] + n_solve * k["solve"]
+            + (n_steps + n_rej + n_fail) * k["att"] + n_steps * k["acc"] + n_resc * k["resc"])
+
+
+def total_flops(spec, counters: np.ndarray) -> float:
+    return float(cell_flops(spec, counters).sum())

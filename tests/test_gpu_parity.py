@@ -1,0 +1,152 @@
+"""GPU burn (through the C ABI) against the CPU oracle on the same seeded
+inputs: element by element on small and ragged batches, on sampled cells of
+the full 65,536-cell workload in the benchmark's launch configuration, on
+every kernel shape, with rate multipliers, and on the failure paths."""
+import numpy as np
+import pytest
+
+from paper_2312_02836_amd import synth
+from tests.parity import compare, summary
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-6, 1e-10
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2312_02836_amd import burn as B
+    return B
+
+
+def _run_both(B, oracle, spec, cells, t_end, rtol=RTOL, atol=ATOL, log_mult=None, **kw):
+    net = B.Network(spec)
+    Yg, Tg, stg, cntg = B.burn(net, cells.Y, cells.rho, cells.T, t_end, rtol, atol,
+                               log_mult=log_mult, **kw)
+    import torch
+    torch.cuda.synchronize()
+    g = (Yg.cpu().numpy(), Tg.cpu().numpy(), stg.cpu().numpy(), cntg.cpu().numpy())
+    o = oracle.burn(oracle.OracleNet(spec), cells, t_end, rtol, atol, log_mult=log_mult,
+                    max_steps=kw.get("max_steps", 0) or 100000)
+    net.close()
+    return g, o
+
+
+def _assert_parity(g, o, rtol=RTOL, atol=ATOL, min_counter_equal=0.99):
+    rep = compare(*g, *o, rtol, atol)
+    print(summary(rep), flush=True)
+    assert rep["status_equal"], "per-cell status differs"
+    assert rep["n_violations"] == 0, (summary(rep), rep["violating_cells"][:10])
+    assert rep["counter_equal_frac"] >= min_counter_equal, summary(rep)
+    return rep
+
+
+def _random_cells(spec, n, seed, T_range=(1.0, 3.0), rho_range=(1.0, 10.0)):
+    y0 = np.zeros(spec.n_species)
+    y0[0] = 1.0
+    return synth.draw_cells(seed, spec, n, T_range=T_range, rho_range=rho_range, y0=y0)
+
+
+@pytest.mark.parametrize("name", ["chain4", "pair1", "pair2"])
+def test_small_networks(gpu, oracle, name):
+    spec = {"chain4": synth.chain_network([3.0, 0.7, 0.05], q=[1.0, 2.0, 0.5]),
+            "pair1": synth.reversible_pair(3.0, 0.5),
+            "pair2": synth.reversible_pair(2.0, 0.3, two_body=True)}[name]
+    cells = _random_cells(spec, 300, 5)
+    g, o = _run_both(gpu, oracle, spec, cells, 5.0)
+    _assert_parity(g, o)
+
+
+def test_robertson_all_cells(gpu, oracle):
+    cfg = synth.config(1)
+    g, o = _run_both(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end)
+    _assert_parity(g, o)
+    assert np.all(g[2] == 0)
+
+
+def test_synth13_ragged(gpu, oracle):
+    """4,099 cells: several workgroups and a ragged last wave."""
+    cfg = synth.config(2, n_cells=4099)
+    g, o = _run_both(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end)
+    _assert_parity(g, o)
+
+
+@pytest.mark.parametrize("lanes", [8, 16])
+def test_synth13_every_shape(gpu, oracle, lanes):
+    cfg = synth.config(2, n_cells=515)
+    g, o = _run_both(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end, lanes_per_cell=lanes)
+    _assert_parity(g, o)
+
+
+def test_synth13_full_size_sampled(gpu, oracle):
+    """The benchmark workload (65,536 cells, default launch shape) on the GPU;
+    the oracle recomputes a seeded sample of 2,048 cells one by one."""
+    import torch
+    cfg = synth.config(2)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = gpu.Network(spec)
+    Yg, Tg, stg, cntg = gpu.burn(net, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(0).choice(cells.n_cells, 2048, replace=False))
+    sub = cells.subset(idx)
+    o = oracle.burn(oracle.OracleNet(spec), sub, cfg.t_end, RTOL, ATOL)
+    g = (Yg.cpu().numpy()[:, idx], Tg.cpu().numpy()[idx], stg.cpu().numpy()[idx],
+         cntg.cpu().numpy()[:, idx])
+    _assert_parity(g, o)
+    assert np.all(stg.cpu().numpy() == 0)
+    net.close()
+
+
+def test_log_multipliers(gpu, oracle):
+    cfg = synth.config(2, n_cells=700)
+    lm = np.random.default_rng(3).normal(0.0, 0.5, cfg.networks[0].n_reactions)
+    g, o = _run_both(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end, log_mult=lm)
+    _assert_parity(g, o)
+
+
+def test_tight_tolerance(gpu, oracle):
+    cfg = synth.config(2, n_cells=300)
+    g, o = _run_both(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end, rtol=1e-9, atol=1e-14)
+    # At rtol 1e-9 the controller's tests sit closer to rounding level, so a
+    # few more cells take a different (equally valid) decision sequence.
+    _assert_parity(g, o, rtol=1e-9, atol=1e-14, min_counter_equal=0.95)
+
+
+def test_failure_paths(gpu, oracle):
+    cfg = synth.config(2, n_cells=64)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    bad = synth.Cells(cells.Y.copy(), cells.rho.copy(), cells.T.copy())
+    bad.rho[3] = np.nan
+    bad.T[5] = 0.0
+    bad.T[6] = -1.0
+    bad.Y[2, 7] = np.inf
+    g, o = _run_both(gpu, oracle, spec, bad, cfg.t_end)
+    _assert_parity(g, o)
+    assert list(np.nonzero(g[2])[0]) == [3, 5, 6, 7] and np.all(g[2][[3, 5, 6, 7]] == 4)
+    # step budget
+    g, o = _run_both(gpu, oracle, spec, cells, cfg.t_end, max_steps=3)
+    _assert_parity(g, o)
+    assert np.all(g[2] == 1) and np.all(g[3][0] == 3)
+    # overflowing rates at the initial state
+    big = synth.NetworkSpec.from_json(spec.to_json())
+    big.coef[0, 0] = 800.0
+    g, o = _run_both(gpu, oracle, big, cells, cfg.t_end)
+    _assert_parity(g, o)
+    assert np.all(g[2] == 3)
+
+
+def test_empty_and_determinism(gpu, oracle):
+    import torch
+    cfg = synth.config(2, n_cells=257)
+    net = gpu.Network(cfg.networks[0])
+    c = cfg.cells[0]
+    out0 = gpu.burn(net, c.Y[:, :0], c.rho[:0], c.T[:0], cfg.t_end)
+    assert out0[0].shape == (13, 0)
+    a = gpu.burn(net, c.Y, c.rho, c.T, cfg.t_end)
+    b = gpu.burn(net, c.Y, c.rho, c.T, cfg.t_end)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[3], b[3])
+    net.close()
