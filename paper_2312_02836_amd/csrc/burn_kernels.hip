@@ -167,6 +167,23 @@ __device__ __forceinline__ void gargmax(double &v, int &p) {
   }
 }
 
+// Arg-max with a payload: max of v, ties to the smallest p; w travels with
+// the winner.
+template <int G, int LV = 0>
+__device__ __forceinline__ void gargmax3(double &v, int &p, int &w) {
+  if constexpr (LV < n_levels<G>()) {
+    const double ov = xch<G, LV>(v);
+    const int op = xch_i<G, LV>(p);
+    const int ow = xch_i<G, LV>(w);
+    if (ov > v || (ov == v && op < p)) {
+      v = ov;
+      p = op;
+      w = ow;
+    }
+    gargmax3<G, LV + 1>(v, p, w);
+  }
+}
+
 // Calls f.template operator()<I>() for I = 0..N-1 (compile-time indices).
 template <int N>
 struct Unroll {
@@ -189,10 +206,12 @@ struct Unroll<0> {
 //   rtab[R*8] emult[R] q[R] qcv[R] roww[nnz] |
 //   rsp[4R] rowoff[N+1] rowr[nnz] coloff[N+1] colent[nsl] | nu8[N*R] | pad
 //   rout[8R] (ints)
-// Per wave: D[CPW][DROWS][NP] ybuf[CPW][NP] facc[CPW][NP] fbuf[FC][FB] fsc[FC][4]
-// with FB = NP + NP*NP + 2*NP doubles per factorization slot: y_J (later the
-// pivot row), the Newton matrix (later the factors in position order) and
-// two auxiliary rows.
+// Per wave: D[CPW][DS] ybuf[CPW][YS] facc[CPW][YS] fbuf[FC][FB] fsc[FC][4]
+// with FB = NP + NP*MS + 2*NP + 1 doubles per factorization slot: y_J (later
+// the pivot row), the Newton matrix with row stride MS (later the factors in
+// position order) and two auxiliary rows.  The per-cell strides DS and YS are
+// 4 doubles more than a multiple of 16 and the matrix row stride MS is odd, so
+// the cells of a wave (and the rows of a matrix) fall in different LDS banks.
 // ---------------------------------------------------------------------------
 
 struct TabSizes {
@@ -212,9 +231,12 @@ struct Shape {
   static constexpr int FL = NP;       // factor lanes per cell (one row each)
   static constexpr int FC = 64 / NP;  // cells per factorization pass
   static_assert(NP == 4 || NP == 8 || NP == 16 || NP == 32 || NP == 64, "NP must be a power of 2");
-  __host__ __device__ static size_t fb(int) { return (size_t)NP * NP + 3 * NP; }
+  static constexpr int DS = DROWS * NP + 4;  // history stride per cell
+  static constexpr int YS = NP + 4;          // exchange-vector stride per cell
+  static constexpr int MS = NP + 1;          // matrix row stride
+  __host__ __device__ static size_t fb(int) { return (size_t)NP * MS + 3 * NP + 1; }
   __host__ __device__ static size_t wave_doubles(int R) {
-    return (size_t)CPW * DROWS * NP + 2 * (size_t)CPW * NP + FC * fb(R) + 4 * FC;
+    return (size_t)CPW * DS + 2 * (size_t)CPW * YS + FC * fb(R) + 4 * FC;
   }
 };
 
@@ -223,6 +245,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W))
 burn_plain_kernel(BurnArgs a, int block_waves) {
   using SH = Shape<L, S>;
   constexpr int NP = SH::NP, CPW = SH::CPW, FL = SH::FL, FC = SH::FC;
+  constexpr int DS = SH::DS, YS = SH::YS, MS = SH::MS;
   extern __shared__ double smem[];
 
   const NetTables &nt = a.net;
@@ -274,10 +297,10 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
   const bool in_range = cell < C;
 
   double *wb = smem + ts.doubles() + (size_t)wave * SH::wave_doubles(R);
-  double *Dl = wb + (size_t)cw * DROWS * NP;  // this cell's history, [DROWS][NP]
-  double *ybuf = wb + (size_t)CPW * DROWS * NP + (size_t)cw * NP;
-  double *facc = wb + (size_t)CPW * DROWS * NP + (size_t)CPW * NP + (size_t)cw * NP;
-  double *fbase = wb + (size_t)CPW * DROWS * NP + 2 * (size_t)CPW * NP;
+  double *Dl = wb + (size_t)cw * DS;  // this cell's history, [DROWS][NP]
+  double *ybuf = wb + (size_t)CPW * DS + (size_t)cw * YS;
+  double *facc = wb + (size_t)CPW * DS + (size_t)CPW * YS + (size_t)cw * YS;
+  double *fbase = wb + (size_t)CPW * DS + 2 * (size_t)CPW * YS;
   double *fsc = fbase + (size_t)FC * SH::fb(R);
 
   const double rtol = a.rtol, atol = a.atol, t_end = a.t_end;
@@ -375,12 +398,14 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       if (sp[1] >= 0) v *= ybuf[sp[1]];
       if (sp[2] >= 0) v *= ybuf[sp[2]];
       heat += s_q[r] * v;
-      const int *ro = s_rout + 8 * r;
-      const int ne = ro[0];
-      for (int e = 1; e <= ne; ++e) {
-        const int ent = ro[e];
-        __hip_atomic_fetch_add(&facc[ent >> 8], (double)(signed char)(ent & 0xff) * v,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      const int4 *ro = reinterpret_cast<const int4 *>(s_rout + 8 * r);
+      const int4 r0 = ro[0], r1 = ro[1];
+      const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        if (e < r0.x)
+          __hip_atomic_fetch_add(&facc[ent[e] >> 8], (double)(signed char)(ent[e] & 0xff) * v,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       }
     };
     for (int r = q; r < R; r += 2 * L) {
@@ -456,31 +481,6 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
     }
   }
 
-  // Newton failure: refresh a stale Jacobian at the predicted state and
-  // retry, else halve the step.  Returns the pending step-change ratio.
-  auto newton_fail = [&]() __attribute__((always_inline)) -> double {
-    cnt[CNT_NFAIL]++;
-    if (!jac_cur) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        yJ[s] = yp[s];
-        dd[s] = 0.0;
-        yv[s] = yp[s];
-      }
-      cnt[CNT_JAC]++;
-      jac_cur = 1;
-      lu_ok = 0;
-      it = 0;
-      fresh_newton = 1;
-      return 0.0;
-    }
-    h *= 0.5;
-    n_eq = 0;
-    lu_ok = 0;
-    need_attempt = 1;
-    return 0.5;
-  };
-
   while (true) {
     // ---------------- A: start of a step attempt ----------------
     if (phase == PH_NEWTON && need_attempt) {
@@ -489,7 +489,9 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
         phase = PH_DONE;
       } else {
         // step underflow (also catches a non-finite h, so every cell ends)
-        const double ulp = nextafter(t, INFINITY) - t;
+        // 10 ulp(t) for t >= 0: the next double above t, minus t
+        const double ulp =
+            __builtin_bit_cast(double, __builtin_bit_cast(long long, t) + 1LL) - t;
         if (!(h >= 10.0 * ulp)) {
           status = 2;
           phase = PH_DONE;
@@ -502,10 +504,13 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
             n_eq = 0;
             lu_ok = 0;
           }
-          double gk = 1.0;
+          double gk = 1.0, igk = 1.0;
 #pragma unroll
           for (int kk = 1; kk <= KMAX; ++kk)
-            if (kk == k) gk = gamma_of(kk);
+            if (kk == k) {
+              gk = gamma_of(kk);
+              igk = 1.0 / gamma_of(kk);
+            }
 #pragma unroll
           for (int s = 0; s < S; ++s) {
             const int i = comp(s);
@@ -520,7 +525,7 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
               }
             }
             yp[s] = sa;
-            psi[s] = sb / gk;
+            psi[s] = sb * igk;
             isc[s] = 1.0 / (atol + rtol * fabs(sa));
             dd[s] = 0.0;
             yv[s] = sa;
@@ -571,11 +576,11 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       for (int j = 0; j < FC; ++j)
         if (j == fj) fsel = sel[j];
       double *fy = fbase + (size_t)fj * SH::fb(R);
-      double *fM = fy + NP;  // Newton matrix [NP][NP], row-major
+      double *fM = fy + NP;  // Newton matrix [NP][MS], row-major
       const double fcc = fsel >= 0 ? fsc[4 * fj + 0] : 0.0;
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) fM[fi * NP + j] = (fi == j) ? 1.0 : 0.0;
+      for (int j = 0; j < NP; ++j) fM[fi * MS + j] = (fi == j) ? 1.0 : 0.0;
       wave_lds_sync();
       // Rates at y_J for the reactions r = fi, fi+FL, ...; every Jacobian term
       // W(i, r) dR_r/dy_j (W = nu for a species row, q/c_v for the temperature
@@ -614,77 +619,70 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
           if (sp[2] >= 0) g[1] *= yc;
           if (sp[0] >= 0) g[2] *= ya;
           if (sp[1] >= 0) g[2] *= yb;
-          const int *ro = s_rout + 8 * r;
-          const int ne = ro[0];
+          const int4 *ro = reinterpret_cast<const int4 *>(s_rout + 8 * r);
+          const int4 r0 = ro[0], r1 = ro[1];
+          const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
           const double qc = s_qcv[r];
 #pragma unroll
           for (int aa = 0; aa < 4; ++aa) {
             const int col = (aa < 3) ? sp[aa] : N;
-            if (col < 0) continue;
-            if (!isfinite(g[aa])) jbad = 1;
-            const double val = -fcc * g[aa];
-            for (int e = 1; e <= ne; ++e) {
-              const int ent = ro[e];
-              __hip_atomic_fetch_add(&fM[(ent >> 8) * NP + col],
-                                     (double)(signed char)(ent & 0xff) * val, __ATOMIC_RELAXED,
+            if (col >= 0) {
+              if (!isfinite(g[aa])) jbad = 1;
+              const double val = -fcc * g[aa];
+#pragma unroll
+              for (int e = 0; e < 6; ++e) {
+                if (e < r0.x)
+                  __hip_atomic_fetch_add(&fM[(ent[e] >> 8) * MS + col],
+                                         (double)(signed char)(ent[e] & 0xff) * val,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+              }
+              __hip_atomic_fetch_add(&fM[N * MS + col], qc * val, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
-            __hip_atomic_fetch_add(&fM[N * NP + col], qc * val, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
           }
         }
       }
       jbad = gor<FL>(jbad);
       wave_lds_sync();
-      double Mr[NP];
-#pragma unroll
-      for (int j = 0; j < NP; ++j) Mr[j] = fM[fi * NP + j];
-      // (c) LU with partial pivoting, one row per lane; `pos` is the position
-      // the row would hold after the textbook row swaps.
+      // (c) LU with partial pivoting on the matrix in LDS, one row per lane.
+      // Rows are not moved: `pos` is the position the row would hold after the
+      // textbook row swaps (the first largest |pivot| in position order wins).
       int pos = fi;
       int fsing = 0;
       double fdinv = 1.0;
-      double *prow = fy;  // pivot-row exchange area (y_J and G are dead now)
-      Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
-        if (K < n) {
-          double v = -2.0;
-          int nan_k = 0;
-          if (pos >= K) {
-            v = fabs(Mr[K]);
-            if (v != v) {
-              if (pos == K) nan_k = 1;
-              v = -1.0;
-            }
+      double *Mrow = fM + fi * MS;
+      for (int K = 0; K < n; ++K) {
+        double v = -2.0;
+        int nan_k = 0;
+        if (pos >= K) {
+          v = fabs(Mrow[K]);
+          if (v != v) {
+            if (pos == K) nan_k = 1;
+            v = -1.0;
           }
-          int bp = (pos >= K) ? pos : (1 << 30);
-          gargmax<FL>(v, bp);
-          nan_k = gor<FL>(nan_k);
-          if (!(v > 0.0) || nan_k) fsing = 1;
-          if (pos == K) pos = bp;
-          else if (pos == bp) pos = K;
-          if (pos == K) {
-#pragma unroll
-            for (int j = K; j < NP; ++j) prow[j] = Mr[j];
-          }
-          wave_lds_sync();
-          const double rinv = 1.0 / prow[K];
-          if (pos == K) fdinv = rinv;
-          if (pos > K) {
-            const double l = Mr[K] * rinv;
-            Mr[K] = l;
-#pragma unroll
-            for (int j = K + 1; j < NP; ++j) Mr[j] -= l * prow[j];
-          }
-          wave_lds_sync();
         }
-      });
-      // (d) hand the rows back in position order
-      double *ftr = fM;
+        int bp = (pos >= K) ? pos : (1 << 30);
+        int prow_i = fi;  // physical row of the pivot (payload of the arg-max)
+        gargmax3<FL>(v, bp, prow_i);
+        nan_k = gor<FL>(nan_k);
+        if (!(v > 0.0) || nan_k) fsing = 1;
+        if (pos == K) pos = bp;
+        else if (pos == bp) pos = K;
+        const double *P = fM + prow_i * MS;
+        const double rinv = 1.0 / P[K];
+        if (pos == K) fdinv = rinv;
+        if (pos > K) {
+          const double l = Mrow[K] * rinv;
+          Mrow[K] = l;
+          for (int j = K + 1; j < n; ++j) Mrow[j] -= l * P[j];
+        }
+        wave_lds_sync();
+      }
+      // (d) the factors stay in LDS; publish position -> row and 1/U_pp
+      double *aux = fM + NP * MS;
       if (fsel >= 0) {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) ftr[pos * NP + j] = Mr[j];
-        ftr[NP * NP + pos] = fdinv;
-        ftr[NP * NP + NP + pos] = (double)fi;
+        aux[pos] = fdinv;
+        aux[NP + pos] = (double)fi;
         if (fi == 0) {
           fsc[4 * fj + 2] = (double)fsing;
           fsc[4 * fj + 3] = (double)jbad;
@@ -696,10 +694,11 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int p = comp(s);
+          dinv[s] = src[NP * MS + p];
+          ridx[s] = (int)src[NP * MS + NP + p];
+          const double *row = src + ridx[s] * MS;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) LU[s][j] = src[p * NP + j];
-          dinv[s] = src[NP * NP + p];
-          ridx[s] = (int)src[NP * NP + NP + p];
+          for (int j = 0; j < NP; ++j) LU[s][j] = row[j];
         }
         sing = fsc[4 * myslot + 2] != 0.0;
         if (first_jac && fsc[4 * myslot + 3] != 0.0) {
@@ -717,17 +716,12 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
     }
 
     double pend = 0.0;
-    int skip_rhs = 0;
-    if (want && phase == PH_NEWTON && sing) {
-      // a singular Newton matrix is a failed Newton attempt
-      fresh_newton = 0;
-      pend = newton_fail();
-      skip_rhs = 1;
-    }
-    if (!skip_rhs) fresh_newton = 0;
+    // a singular Newton matrix is a failed Newton attempt (no RHS needed)
+    int nfail = (want && phase == PH_NEWTON && sing) ? 1 : 0;
+    fresh_newton = 0;
 
     // ---------------- C: right-hand side ----------------
-    const int do_rhs = (phase != PH_DONE) && !skip_rhs;
+    const int do_rhs = (phase != PH_DONE) && !nfail;
     int okf = 1;
     if (do_rhs) {
       okf = rhs();
@@ -832,7 +826,7 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
           }
         }
         if (fail) {
-          pend = newton_fail();
+          nfail = 1;
         } else if (converged) {
           // error test, scale atol + rtol * max(|y_n|, |y_new|)
           double e1[S];
@@ -910,6 +904,30 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
             }
           }
         }
+      }
+    }
+    // Newton failure: refresh a stale Jacobian at the predicted state and
+    // retry with the same step, else halve the step.
+    if (nfail) {
+      cnt[CNT_NFAIL]++;
+      if (!jac_cur) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          yJ[s] = yp[s];
+          dd[s] = 0.0;
+          yv[s] = yp[s];
+        }
+        cnt[CNT_JAC]++;
+        jac_cur = 1;
+        lu_ok = 0;
+        it = 0;
+        fresh_newton = 1;
+      } else {
+        h *= 0.5;
+        n_eq = 0;
+        lu_ok = 0;
+        need_attempt = 1;
+        pend = 0.5;
       }
     }
     if (pend != 0.0 && phase == PH_NEWTON) rescale(k, pend);
