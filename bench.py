@@ -19,6 +19,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
+KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_kernels.hip",
+                  "paper_2312_02836_amd/csrc/burn_internal.h"]
+TRAFFIC_FILE = "profiles/burn_plain_kernel__synth13_30__65536cells__hbm_traffic.txt"
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the burn kernel from the committed FETCH_SIZE /
+    WRITE_SIZE passes, or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def main() -> int:
@@ -31,6 +60,9 @@ def main() -> int:
     ap.add_argument("--block-waves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size before the warmup "
+                         "(calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the burn needs no communication; "
@@ -68,6 +100,17 @@ def main() -> int:
                              C.c_void_p(cnt.data_ptr()), C.byref(opts),
                              C.c_void_p(stream.cuda_stream))
         _lib.check(rc, "burn_batch_ex")
+
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: copy probe {nb} bytes read + {nb} bytes written", file=sys.stderr,
+              flush=True)
+        del src, dst
 
     for _ in range(args.warmup):
         Yw.copy_(Y0)
@@ -141,7 +184,9 @@ def main() -> int:
                    "t_end": cfg.t_end, "kernel": "burn_plain_kernel",
                    "lanes_per_cell": args.lanes or "auto"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": (measured_traffic() if (args.cells, args.lanes, args.block_waves) == (65536, 0, 0)
+                                 else None),
                      "kernel_ms": kernel_avg_ms, "alg_flops_per_launch": f_launch},
         "cpu_baseline": cpu,
     }
