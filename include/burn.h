@@ -69,7 +69,7 @@ extern "C" {
 #define BN_MAX_SYSTEM 64
 #define BN_MAX_REACTIONS 1024
 
-typedef struct bn_network bn_network; /* opaque, immutable after create */
+typedef struct bn_network bn_network; /* opaque; tables immutable after create */
 
 /* Network description (all HOST pointers, read during bn_network_create). */
 typedef struct {
@@ -119,7 +119,8 @@ int burn_batch(const bn_network *net, int64_t n_cells, double *state, const doub
 /* Optional knobs for burn_batch_ex (zero-initialise, then set fields). */
 typedef struct {
   int32_t max_steps;      /* accepted-step budget per cell; <= 0 means 100000 */
-  int32_t lanes_per_cell; /* 0 = automatic; otherwise 4, 8, 16 or 64 (tuning) */
+  int32_t lanes_per_cell; /* 0 = the network's launch choice (tuned or default);
+                             otherwise 4, 8, 16, 32 or 64 */
   int32_t block_waves;    /* 0 = automatic; waves per workgroup (tuning) */
   int32_t reserved;
 } bn_burn_opts;
@@ -128,6 +129,80 @@ typedef struct {
 int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const double *rho,
                   double *T, double dt, double rtol, double atol, const double *log_mult,
                   int32_t *status, int32_t *counters, const bn_burn_opts *opts, void *stream);
+
+/* ---- Persistent multi-network burn ------------------------------------ */
+
+/* One network's batch of cells inside a multi-network launch.  The arrays
+ * follow the conventions of burn_batch. */
+typedef struct {
+  const bn_network *net;
+  int64_t n_cells;
+  double *state;          /* DEVICE [N][n_cells], in/out */
+  const double *rho;      /* DEVICE [n_cells] */
+  double *T;              /* DEVICE [n_cells], in/out */
+  const double *log_mult; /* DEVICE [R] or NULL */
+  int32_t *status;        /* DEVICE [n_cells] or NULL */
+  int32_t *counters;      /* DEVICE [BN_N_COUNTERS][n_cells] or NULL */
+} bn_batch_item;
+
+#define BN_MAX_ITEMS 8
+
+/* Device workspace burn_batch_multi needs for n_items items (one 8-byte
+ * queue counter per item, rounded up to 256 bytes). */
+size_t burn_batch_multi_workspace_bytes(int32_t n_items);
+
+/* Burn the cells of up to BN_MAX_ITEMS networks (same dt and tolerances) in
+ * ONE persistent kernel launch with a device work queue: the grid is sized to
+ * the GPU, and each lane group that finishes a cell takes the next unstarted
+ * cell of the current network, so cells of uneven stiffness and networks of
+ * different sizes share the machine without per-batch tails.  Per-cell
+ * results are bitwise identical to burn_batch with the same launch shape (a
+ * cell's arithmetic depends on the shape, never on where or when it runs).
+ *   items      HOST [n_items]   the batches (networks on the current device)
+ *   opts       HOST or NULL     max_steps and block_waves are honoured;
+ *                               lanes_per_cell must be 0 (each network uses its
+ *                               launch choice, see bn_network_autotune)
+ *   workspace  DEVICE           >= burn_batch_multi_workspace_bytes(n_items)
+ *                               bytes, 8-byte aligned, caller-owned; it must
+ *                               not be used by another launch in flight
+ * The call enqueues a small counter-reset kernel and the burn kernel on
+ * `stream` and nothing else (no allocation, no memset, no synchronization),
+ * so a sequence of calls can be captured into a HIP graph and replayed.
+ * Returns BN_SUCCESS or a negative code (nothing enqueued). */
+int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, double rtol,
+                     double atol, const bn_burn_opts *opts, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* ---- Launch-shape autotuner -------------------------------------------- */
+
+typedef struct {
+  int32_t lanes_per_cell; /* L: lanes that own one cell */
+  int32_t slots_per_lane; /* S: system components per lane (n <= L*S) */
+  int32_t block_waves;    /* waves per workgroup */
+  int32_t status;         /* 0 measured, else the launch error (skipped) */
+  double ms;              /* kernel time on the sample */
+} bn_tune_result;
+
+/* Time every launch shape that fits this network on a sample of cells (the
+ * caller's arrays are only read: the sample is burned in library-allocated
+ * scratch copies) and make the fastest the network's launch choice, used by
+ * burn_batch (lanes_per_cell = 0) and burn_batch_multi.  Synchronizes
+ * `stream`; allocates device memory; not for use under graph capture.
+ *   state, rho, T  DEVICE sample in the burn_batch layout (n_cells >= 1)
+ *   results        HOST [max_results] or NULL; *n_results = entries written
+ * Returns BN_SUCCESS or a negative code. */
+int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
+                        const double *rho, const double *T, double dt, double rtol,
+                        double atol, const double *log_mult, int32_t max_steps,
+                        bn_tune_result *results, int32_t max_results, int32_t *n_results,
+                        void *stream);
+
+/* Set / read the network's launch choice directly (e.g. from a cached
+ * tuning).  Setting validates the shape against the system size. */
+int bn_network_set_launch(bn_network *net, int32_t lanes_per_cell, int32_t slots_per_lane,
+                          int32_t block_waves);
+int bn_network_get_launch(const bn_network *net, int32_t *lanes_per_cell,
+                          int32_t *slots_per_lane, int32_t *block_waves);
 
 /* Thread-local description of the last failed call on this thread ("" if
  * none); valid until the next call from the same thread. */

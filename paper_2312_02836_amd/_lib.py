@@ -20,7 +20,10 @@ COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "
 
 # Every symbol include/burn.h declares.
 EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
-           "bn_network_n_reactions", "burn_batch", "burn_batch_ex", "bn_last_error", "bn_version"]
+           "bn_network_n_reactions", "burn_batch", "burn_batch_ex",
+           "burn_batch_multi_workspace_bytes", "burn_batch_multi", "bn_network_autotune",
+           "bn_network_set_launch", "bn_network_get_launch", "bn_last_error", "bn_version"]
+MAX_ITEMS = 8
 
 
 class NetworkDesc(C.Structure):
@@ -33,6 +36,17 @@ class NetworkDesc(C.Structure):
 class BurnOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
                 ("block_waves", C.c_int32), ("reserved", C.c_int32)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("net", C.c_void_p), ("n_cells", C.c_int64), ("state", C.c_void_p),
+                ("rho", C.c_void_p), ("T", C.c_void_p), ("log_mult", C.c_void_p),
+                ("status", C.c_void_p), ("counters", C.c_void_p)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("lanes_per_cell", C.c_int32), ("slots_per_lane", C.c_int32),
+                ("block_waves", C.c_int32), ("status", C.c_int32), ("ms", C.c_double)]
 
 
 class BurnError(RuntimeError):
@@ -62,6 +76,20 @@ def lib() -> C.CDLL:
     L.burn_batch_ex.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                 dp, ip, ip, C.POINTER(BurnOpts), vp]
     L.burn_batch_ex.restype = C.c_int
+    L.burn_batch_multi_workspace_bytes.argtypes = [C.c_int32]
+    L.burn_batch_multi_workspace_bytes.restype = C.c_size_t
+    L.burn_batch_multi.argtypes = [C.c_int32, C.POINTER(BatchItem), C.c_double, C.c_double,
+                                   C.c_double, C.POINTER(BurnOpts), vp, C.c_size_t, vp]
+    L.burn_batch_multi.restype = C.c_int
+    L.bn_network_autotune.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
+                                      C.c_double, dp, C.c_int32, C.POINTER(TuneResult),
+                                      C.c_int32, C.POINTER(C.c_int32), vp]
+    L.bn_network_autotune.restype = C.c_int
+    L.bn_network_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    L.bn_network_set_launch.restype = C.c_int
+    L.bn_network_get_launch.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32)]
+    L.bn_network_get_launch.restype = C.c_int
     L.bn_last_error.restype = C.c_char_p
     L.bn_version.restype = C.c_char_p
     _lib = L

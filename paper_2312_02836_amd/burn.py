@@ -36,6 +36,17 @@ class Network:
         _lib.check(_lib.lib().bn_network_create(C.byref(desc), C.byref(h)), "bn_network_create")
         self.handle = h
 
+    def set_launch(self, lanes_per_cell: int, slots_per_lane: int, block_waves: int = 0) -> None:
+        """Fix the launch shape (0 lanes = back to the default)."""
+        _lib.check(_lib.lib().bn_network_set_launch(self.handle, lanes_per_cell, slots_per_lane,
+                                                    block_waves), "bn_network_set_launch")
+
+    def get_launch(self) -> Tuple[int, int, int]:
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(_lib.lib().bn_network_get_launch(self.handle, C.byref(a), C.byref(b),
+                                                    C.byref(c)), "bn_network_get_launch")
+        return a.value, b.value, c.value
+
     @property
     def n_species(self) -> int:
         return self.spec.n_species
@@ -101,3 +112,116 @@ def burn(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float = 1
                                   C.byref(opts), C.c_void_p(stream))
     _lib.check(rc, "burn_batch_ex")
     return Yd, Td, st, cnt
+
+
+def _prep_batch(net: Network, Y, rho, T, log_mult, device, inplace, want_status, want_counters):
+    if inplace:
+        Yd, Td = Y, T
+        for t in (Yd, Td):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+                raise ValueError("inplace needs contiguous float64 device tensors")
+    else:
+        Yd = _dev_f64(Y, device).clone()
+        Td = _dev_f64(T, device).clone()
+    rhod = _dev_f64(rho, device)
+    C_ = rhod.shape[0]
+    if Yd.shape != (net.n_species, C_) or Td.shape != (C_,):
+        raise ValueError(f"shapes: Y {tuple(Yd.shape)}, T {tuple(Td.shape)}, rho {tuple(rhod.shape)}")
+    lm = None if log_mult is None else _dev_f64(log_mult, device)
+    if lm is not None and lm.shape != (net.n_reactions,):
+        raise ValueError("log_mult must have one entry per reaction")
+    st = torch.empty(C_, dtype=torch.int32, device=device) if want_status else None
+    cnt = torch.empty((8, C_), dtype=torch.int32, device=device) if want_counters else None
+    return Yd, rhod, Td, lm, st, cnt
+
+
+class MultiBurn:
+    """A persistent multi-network burn: up to 8 (network, cells) batches in
+    one kernel launch with a device work queue.
+
+    The device arrays are bound at construction (float64 contiguous device
+    tensors, updated in place), so ``run()`` enqueues exactly a counter-reset
+    kernel and the burn kernel on the current stream: it allocates nothing
+    and can be captured into a graph (``capture()``) and replayed.
+    """
+
+    def __init__(self, batches, dt: float, rtol: float = 1e-6, atol: float = 1e-10, *,
+                 max_steps: int = 0, block_waves: int = 0, want_status: bool = True,
+                 want_counters: bool = True, device: Optional[torch.device] = None):
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        if len(batches) > _lib.MAX_ITEMS:
+            raise ValueError(f"at most {_lib.MAX_ITEMS} batches per launch")
+        self.dt, self.rtol, self.atol = float(dt), float(rtol), float(atol)
+        self.opts = _lib.BurnOpts(int(max_steps), 0, int(block_waves), 0)
+        self.outputs = []
+        items = (_lib.BatchItem * max(1, len(batches)))()
+        for j, b in enumerate(batches):
+            net, Y, rho, T = b[:4]
+            lm = b[4] if len(b) > 4 else None
+            Yd, rhod, Td, lmd, st, cnt = _prep_batch(net, Y, rho, T, lm, device, True,
+                                                     want_status, want_counters)
+            self.outputs.append((Yd, Td, st, cnt, rhod, lmd))
+            items[j] = _lib.BatchItem(net.handle.value, rhod.shape[0], Yd.data_ptr(),
+                                      rhod.data_ptr(), Td.data_ptr(),
+                                      lmd.data_ptr() if lmd is not None else None,
+                                      st.data_ptr() if st is not None else None,
+                                      cnt.data_ptr() if cnt is not None else None)
+        self.nets = [b[0] for b in batches]  # keep the handles alive
+        self.items, self.n_items = items, len(batches)
+        nb = _lib.lib().burn_batch_multi_workspace_bytes(max(1, self.n_items))
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.graph = None
+
+    def run(self) -> None:
+        stream = torch.cuda.current_stream().cuda_stream
+        rc = _lib.lib().burn_batch_multi(self.n_items, self.items, self.dt, self.rtol, self.atol,
+                                         C.byref(self.opts), C.c_void_p(self.workspace.data_ptr()),
+                                         self.workspace.numel(), C.c_void_p(stream))
+        _lib.check(rc, "burn_batch_multi")
+
+    def capture(self) -> "torch.cuda.CUDAGraph":
+        """Capture run() into a HIP graph (replayed with ``replay()``)."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self) -> None:
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+
+def burn_multi(batches, dt: float, rtol: float = 1e-6, atol: float = 1e-10, **kw):
+    """Burn several (net, Y, rho, T[, log_mult]) batches in one persistent
+    launch; returns [(Y_end, T_end, status, counters), ...] (new tensors)."""
+    device = kw.get("device") or torch.device("cuda", torch.cuda.current_device())
+    own = []
+    for b in batches:
+        net, Y, rho, T = b[:4]
+        lm = b[4] if len(b) > 4 else None
+        own.append((net, _dev_f64(Y, device).clone(), _dev_f64(rho, device),
+                    _dev_f64(T, device).clone(), lm))
+    mb = MultiBurn(own, dt, rtol, atol, **kw)
+    mb.run()
+    return [(o[0], o[1], o[2], o[3]) for o in mb.outputs]
+
+
+def autotune(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float = 1e-10,
+             log_mult=None, *, max_steps: int = 0, device: Optional[torch.device] = None):
+    """Time every launch shape on a sample of cells and make the fastest the
+    network's launch choice.  Returns [(L, S, block_waves, ms or None), ...]."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    Yd, rhod, Td = _dev_f64(Y, device), _dev_f64(rho, device), _dev_f64(T, device)
+    lm = None if log_mult is None else _dev_f64(log_mult, device)
+    res = (_lib.TuneResult * 64)()
+    nres = C.c_int32()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    rc = _lib.lib().bn_network_autotune(net.handle, rhod.shape[0], _ptr(Yd), _ptr(rhod), _ptr(Td),
+                                        float(dt), float(rtol), float(atol), _ptr(lm),
+                                        int(max_steps), res, 64, C.byref(nres),
+                                        C.c_void_p(stream))
+    _lib.check(rc, "bn_network_autotune")
+    return [(r.lanes_per_cell, r.slots_per_lane, r.block_waves, r.ms if r.status == 0 else None)
+            for r in res[:nres.value]]

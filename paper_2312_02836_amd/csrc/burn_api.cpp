@@ -6,16 +6,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "burn_internal.h"
-
-namespace bn {
-size_t plain_lds_bytes(const BurnArgs &a, int L, int S, int block_waves);
-}
 
 struct bn_network {
   int N = 0, R = 0, n = 0, nnz = 0;
@@ -23,6 +21,9 @@ struct bn_network {
   int device = 0;
   void *dev = nullptr;  // one allocation holding every table
   bn::NetTables tables{};
+  // launch choice (0 = default for the system size)
+  int L = 0, S = 0, block_waves = 0;
+  double ms_per_cell = 0.0;  // measured by the autotuner (0 = unknown)
 };
 
 namespace {
@@ -42,6 +43,87 @@ int nu_of(const bn_network_desc *d, int i, int r) {
     v -= (d->reactants[3 * r + s] == i);
   }
   return v;
+}
+
+struct DeviceLimits {
+  size_t lds_block = 64 * 1024;  // dynamic LDS per workgroup
+  size_t lds_cu = 64 * 1024;     // LDS per compute unit
+  int cus = 1;
+};
+
+int device_limits(int dev, DeviceLimits *out) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return fail(BN_EHIP, "hipDeviceGetAttribute(MaxSharedMemoryPerBlock) failed");
+  out->lds_block = (size_t)v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+      hipSuccess)
+    return fail(BN_EHIP, "hipDeviceGetAttribute(MaxSharedMemoryPerMultiprocessor) failed");
+  out->lds_cu = (size_t)v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(BN_EHIP, "hipDeviceGetAttribute(MultiprocessorCount) failed");
+  out->cus = v > 0 ? v : 1;
+  return BN_SUCCESS;
+}
+
+bool plain_shape(int L, int S) {
+  for (const bn::ShapeLS &sh : bn::PLAIN_SHAPES)
+    if (sh.L == L && sh.S == S) return true;
+  return false;
+}
+
+int multi_shape_index(int L, int S) {
+  for (int i = 0; i < bn::N_MULTI_SHAPES; ++i)
+    if (bn::MULTI_SHAPES[i].L == L && bn::MULTI_SHAPES[i].S == S) return i;
+  return -1;
+}
+
+// Default shape for a system of size n (before any tuning).
+void default_shape(int n, int *L, int *S) {
+  if (n <= 4) { *L = 4; *S = 1; }
+  else if (n <= 8) { *L = 4; *S = 2; }
+  else if (n <= 16) { *L = 4; *S = 4; }
+  else if (n <= 32) { *L = 16; *S = 2; }
+  else { *L = 64; *S = 1; }
+}
+
+// Default for the persistent kernel (its shapes are a subset).
+void default_multi_shape(int n, int *L, int *S) {
+  if (n <= 16) { *L = 4; *S = 4; }
+  else if (n <= 32) { *L = 16; *S = 2; }
+  else { *L = 64; *S = 1; }
+}
+
+// Shape for a plain launch: an explicit lanes hint picks the smallest
+// padded size with that L; else the network's choice; else the default.
+bool pick_shape(const bn_network *net, int lanes_hint, int *L, int *S) {
+  if (lanes_hint) {
+    for (const bn::ShapeLS &sh : bn::PLAIN_SHAPES)
+      if (sh.L == lanes_hint && sh.L * sh.S >= net->n) {
+        *L = sh.L;
+        *S = sh.S;
+        return true;
+      }
+    return false;
+  }
+  if (net->L) {
+    *L = net->L;
+    *S = net->S;
+    return true;
+  }
+  default_shape(net->n, L, S);
+  return true;
+}
+
+size_t lds_bytes(int R, int L, int S, int n, int bw) {
+  return bn::table_lds_bytes(R) + (size_t)bw * bn::wave_lds_bytes(L, S, n);
+}
+
+int check_tol(double dt, double rtol, double atol) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BN_EINVAL, "dt must be positive and finite");
+  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(BN_EINVAL, "rtol must be positive");
+  if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(BN_EINVAL, "atol must be >= 0");
+  return BN_SUCCESS;
 }
 
 }  // namespace
@@ -229,24 +311,24 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
   g_err.clear();
   if (!net) return fail(BN_EINVAL, "null network");
   if (n_cells < 0) return fail(BN_EINVAL, "n_cells < 0");
-  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(BN_EINVAL, "dt must be positive and finite");
-  if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(BN_EINVAL, "rtol must be positive");
-  if (!(atol >= 0.0) || !std::isfinite(atol)) return fail(BN_EINVAL, "atol must be >= 0");
-  if (n_cells == 0) return BN_SUCCESS;
-  if (!state || !rho || !T) return fail(BN_EINVAL, "null state, rho or T");
+  if (int rc = check_tol(dt, rtol, atol)) return rc;
   bn_burn_opts o{};
   if (opts) o = *opts;
   if (o.max_steps <= 0) o.max_steps = 100000;
   if (o.lanes_per_cell != 0 && o.lanes_per_cell != 4 && o.lanes_per_cell != 8 &&
-      o.lanes_per_cell != 16 && o.lanes_per_cell != 64)
-    return fail(BN_EINVAL, "lanes_per_cell must be 0, 4, 8, 16 or 64");
+      o.lanes_per_cell != 16 && o.lanes_per_cell != 32 && o.lanes_per_cell != 64)
+    return fail(BN_EINVAL, "lanes_per_cell must be 0, 4, 8, 16, 32 or 64");
   if (o.block_waves < 0 || o.block_waves > 4) return fail(BN_EINVAL, "block_waves must be 0..4");
+  if (n_cells == 0) return BN_SUCCESS;
+  if (!state || !rho || !T) return fail(BN_EINVAL, "null state, rho or T");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
   if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
 
   int L = 0, S = 0;
-  if (!bn::choose_shape(net->n, o.lanes_per_cell, &L, &S))
+  if (!pick_shape(net, o.lanes_per_cell, &L, &S))
     return fail(BN_EUNSUPPORTED, "no kernel shape for this system size and lanes_per_cell");
 
   bn::BurnArgs a{};
@@ -265,11 +347,11 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
 
   int bw = o.block_waves;
   if (bw == 0) {
-    bw = 2;
-    while (bw > 1 && bn::plain_lds_bytes(a, L, S, bw) > 64 * 1024) --bw;
+    bw = (!o.lanes_per_cell && net->block_waves) ? net->block_waves : 2;
+    while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) bw /= 2;
   }
-  if (bn::plain_lds_bytes(a, L, S, bw) > 64 * 1024)
-    return fail(BN_EUNSUPPORTED, "network tables too large for LDS");
+  if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
+    return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
   const hipError_t e = bn::launch_plain(a, L, S, bw, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;
@@ -280,6 +362,254 @@ int burn_batch(const bn_network *net, int64_t n_cells, double *state, const doub
                int32_t *status, int32_t *counters, void *stream) {
   return burn_batch_ex(net, n_cells, state, rho, T, dt, rtol, atol, log_mult, status, counters,
                        nullptr, stream);
+}
+
+
+size_t burn_batch_multi_workspace_bytes(int32_t n_items) {
+  if (n_items < 1) n_items = 1;
+  return (((size_t)n_items * sizeof(unsigned long long)) + 255) / 256 * 256;
+}
+
+int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, double rtol,
+                     double atol, const bn_burn_opts *opts, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  g_err.clear();
+  if (n_items < 0 || n_items > BN_MAX_ITEMS)
+    return fail(BN_EINVAL, "n_items must be 0..BN_MAX_ITEMS");
+  if (n_items > 0 && !items) return fail(BN_EINVAL, "null items");
+  if (int rc = check_tol(dt, rtol, atol)) return rc;
+  bn_burn_opts o{};
+  if (opts) o = *opts;
+  if (o.max_steps <= 0) o.max_steps = 100000;
+  if (o.lanes_per_cell != 0)
+    return fail(BN_EINVAL, "lanes_per_cell must be 0 for burn_batch_multi");
+  if (o.block_waves < 0 || o.block_waves > 4) return fail(BN_EINVAL, "block_waves must be 0..4");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+
+  // validate and collect the non-empty items
+  struct It {
+    bn::BurnArgs a;
+    int shape;
+    double cost;
+  };
+  std::vector<It> its;
+  int64_t total = 0;
+  size_t tabd = 0, waved = 0;
+  for (int j = 0; j < n_items; ++j) {
+    const bn_batch_item &x = items[j];
+    if (!x.net) return fail(BN_EINVAL, "null network in item " + std::to_string(j));
+    if (x.net->device != dev) return fail(BN_EINVAL, "network was created on another device");
+    if (x.n_cells < 0) return fail(BN_EINVAL, "n_cells < 0 in item " + std::to_string(j));
+    if (x.n_cells == 0) continue;
+    if (!x.state || !x.rho || !x.T)
+      return fail(BN_EINVAL, "null state, rho or T in item " + std::to_string(j));
+    int L = x.net->L, S = x.net->S;
+    if (!L || multi_shape_index(L, S) < 0) default_multi_shape(x.net->n, &L, &S);
+    It it{};
+    it.shape = multi_shape_index(L, S);
+    bn::BurnArgs &a = it.a;
+    a.net = x.net->tables;
+    a.n_cells = x.n_cells;
+    a.Y = x.state;
+    a.rho = x.rho;
+    a.T = x.T;
+    a.log_mult = x.log_mult;
+    a.status = x.status;
+    a.counters = x.counters;
+    a.t_end = dt;
+    a.rtol = rtol;
+    a.atol = atol;
+    a.max_steps = o.max_steps;
+    // cost per cell: measured if tuned, else a size model (LU ~ n^3, RHS ~ R)
+    const double n = x.net->n;
+    it.cost = x.net->ms_per_cell > 0.0 ? x.net->ms_per_cell : 1e-6 * (n * n * n + 40.0 * x.net->R);
+    its.push_back(it);
+    total += x.n_cells;
+    tabd = std::max(tabd, bn::table_lds_bytes(x.net->R) / 8);
+    waved = std::max(waved, bn::wave_lds_bytes(L, S, x.net->n) / 8);
+  }
+  if (its.empty()) return BN_SUCCESS;
+  const size_t need = burn_batch_multi_workspace_bytes((int32_t)its.size());
+  if (!workspace || workspace_bytes < need)
+    return fail(BN_EINVAL, "workspace missing or smaller than burn_batch_multi_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % 8)
+    return fail(BN_EINVAL, "workspace must be 8-byte aligned");
+  // costliest cells first, so the tail of the launch is made of cheap cells
+  std::stable_sort(its.begin(), its.end(), [](const It &x, const It &y) { return x.cost > y.cost; });
+
+  bn::MultiArgs m{};
+  m.n_items = (int)its.size();
+  for (int j = 0; j < m.n_items; ++j) {
+    m.item[j] = its[j].a;
+    m.shape[j] = its[j].shape;
+  }
+  m.queue = static_cast<unsigned long long *>(workspace);
+  m.tab_doubles = tabd;
+  m.wave_doubles = waved;
+  // One wave per SIMD (4 per CU).  Workgroups of block_waves waves; as many
+  // workgroups per CU as LDS allows, up to 4 waves per CU.
+  int bw = o.block_waves ? o.block_waves : 4;
+  while (bw > 1 && 8 * (tabd + (size_t)bw * waved) > lim.lds_block) bw /= 2;
+  const size_t lds = 8 * (tabd + (size_t)bw * waved);
+  if (lds > lim.lds_block)
+    return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
+  m.block_waves = bw;
+  int per_cu = std::max(1, 4 / bw);
+  per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, lim.lds_cu / lds));
+  int64_t grid = (int64_t)lim.cus * per_cu;
+  // no more workgroups than there are cells to start
+  const int64_t cells_per_wg = (int64_t)bw * 16;
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, (total + cells_per_wg - 1) / cells_per_wg));
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = bn::launch_zero(m.queue, m.n_items, st);
+  if (e != hipSuccess)
+    return fail(BN_EHIP, std::string("counter reset launch failed: ") + hipGetErrorString(e));
+  e = bn::launch_multi(m, (int)grid, st);
+  if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return BN_SUCCESS;
+}
+
+int bn_network_set_launch(bn_network *net, int32_t lanes_per_cell, int32_t slots_per_lane,
+                          int32_t block_waves) {
+  g_err.clear();
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (lanes_per_cell == 0) {
+    net->L = net->S = net->block_waves = 0;
+    net->ms_per_cell = 0.0;
+    return BN_SUCCESS;
+  }
+  if (!plain_shape(lanes_per_cell, slots_per_lane))
+    return fail(BN_EINVAL, "unknown launch shape");
+  if (lanes_per_cell * slots_per_lane < net->n)
+    return fail(BN_EINVAL, "launch shape smaller than the system");
+  if (block_waves < 0 || block_waves > 4) return fail(BN_EINVAL, "block_waves must be 0..4");
+  net->L = lanes_per_cell;
+  net->S = slots_per_lane;
+  net->block_waves = block_waves;
+  return BN_SUCCESS;
+}
+
+int bn_network_get_launch(const bn_network *net, int32_t *lanes_per_cell,
+                          int32_t *slots_per_lane, int32_t *block_waves) {
+  g_err.clear();
+  if (!net || !lanes_per_cell || !slots_per_lane || !block_waves)
+    return fail(BN_EINVAL, "null argument");
+  int L = net->L, S = net->S;
+  if (!L) default_shape(net->n, &L, &S);
+  *lanes_per_cell = L;
+  *slots_per_lane = S;
+  *block_waves = net->block_waves;
+  return BN_SUCCESS;
+}
+
+int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
+                        const double *rho, const double *T, double dt, double rtol,
+                        double atol, const double *log_mult, int32_t max_steps,
+                        bn_tune_result *results, int32_t max_results, int32_t *n_results,
+                        void *stream) {
+  g_err.clear();
+  if (n_results) *n_results = 0;
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (n_cells < 1) return fail(BN_EINVAL, "autotune needs at least one cell");
+  if (!state || !rho || !T) return fail(BN_EINVAL, "null state, rho or T");
+  if (int rc = check_tol(dt, rtol, atol)) return rc;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t ybytes = (size_t)net->N * n_cells * 8, tbytes = (size_t)n_cells * 8;
+  void *scratch = nullptr;
+  if (hipMalloc(&scratch, ybytes + tbytes + (size_t)n_cells * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BN_ENOMEM, "hipMalloc of the autotune scratch failed");
+  }
+  double *Ys = static_cast<double *>(scratch);
+  double *Ts = Ys + (size_t)net->N * n_cells;
+  int32_t *sts = reinterpret_cast<int32_t *>(Ts + n_cells);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = BN_SUCCESS;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = fail(BN_EHIP, "hipEventCreate failed");
+  }
+  double best = -1.0;
+  int bL = 0, bS = 0, bbw = 0, nres = 0;
+  const int n = net->n;
+  for (int si = 0; rc == BN_SUCCESS && si < bn::N_PLAIN_SHAPES; ++si) {
+    const int L = bn::PLAIN_SHAPES[si].L, S = bn::PLAIN_SHAPES[si].S;
+    const int NP = L * S;
+    if (NP < n || NP >= 4 * n + 16) continue;  // too small, or mostly padding
+    for (int bw = 1; bw <= 4 && rc == BN_SUCCESS; bw *= 2) {
+      if (lds_bytes(net->R, L, S, n, bw) > lim.lds_block) continue;
+      bn::BurnArgs a{};
+      a.net = net->tables;
+      a.n_cells = n_cells;
+      a.Y = Ys;
+      a.rho = rho;
+      a.T = Ts;
+      a.log_mult = log_mult;
+      a.status = sts;
+      a.counters = nullptr;
+      a.t_end = dt;
+      a.rtol = rtol;
+      a.atol = atol;
+      a.max_steps = max_steps > 0 ? max_steps : 100000;
+      double ms = 0.0;
+      hipError_t e = hipSuccess;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms up
+        if ((e = hipMemcpyAsync(Ys, state, ybytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(Ts, T, tbytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+        if ((e = bn::launch_plain(a, L, S, bw, st)) != hipSuccess) break;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float f = 0.0f;
+        if ((e = hipEventElapsedTime(&f, e0, e1)) != hipSuccess) break;
+        ms = f;
+      }
+      if (results && nres < max_results) {
+        results[nres].lanes_per_cell = L;
+        results[nres].slots_per_lane = S;
+        results[nres].block_waves = bw;
+        results[nres].status = (int32_t)e;
+        results[nres].ms = e == hipSuccess ? ms : -1.0;
+      }
+      ++nres;
+      if (e != hipSuccess) {
+        // a launch that does not fit is skipped; anything else is an error
+        if (e == hipErrorInvalidValue || e == hipErrorInvalidConfiguration ||
+            e == hipErrorLaunchOutOfResources) {
+          (void)hipGetLastError();
+          continue;
+        }
+        rc = fail(BN_EHIP, std::string("autotune launch failed: ") + hipGetErrorString(e));
+        break;
+      }
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        bL = L;
+        bS = S;
+        bbw = bw;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(scratch);
+  if (n_results) *n_results = std::min(nres, max_results > 0 ? max_results : 0);
+  if (rc != BN_SUCCESS) return rc;
+  if (best < 0.0) return fail(BN_EUNSUPPORTED, "no launch shape fits this network");
+  net->L = bL;
+  net->S = bS;
+  net->block_waves = bbw;
+  net->ms_per_cell = best / (double)n_cells;
+  return BN_SUCCESS;
 }
 
 }  // extern "C"

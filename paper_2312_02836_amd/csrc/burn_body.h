@@ -1,4 +1,5 @@
-// burn_kernels.hip -- FP64 per-cell reaction-network burn for CDNA4 (gfx950).
+// burn_body.h -- device code of the FP64 per-cell reaction-network burn for
+// CDNA4 (gfx950), shared by the plain and the persistent kernels.
 //
 // What is computed follows the single-zone burn of the paper (Sec. 2: the
 // network right-hand side and analytic Jacobian generated per network and
@@ -20,13 +21,15 @@
 //    with 64/L cells per wave almost every loop iteration has some cell that
 //    needs one.  The cells that need a factorization are therefore batched
 //    into a wave-wide pass in which every cell gets FL = NP lanes, one matrix
-//    row per lane: the Jacobian row is rebuilt from the stored state y_J with
-//    static column indices, the LU runs with row-position tracking (no data
-//    swaps), and the factors go back to the owning group through LDS.
-//  * Control.  Each loop iteration does, per cell: step-attempt setup,
-//    the factorization pass (wave-wide), one right-hand side, and the Newton /
+//    row per lane: the Newton matrix is accumulated in LDS from the
+//    reaction-parallel Jacobian terms, the LU runs in LDS with row-position
+//    tracking (no data swaps), and the factors go back to the owning group.
+//  * Control.  Each loop iteration does, per cell: (0) output of a finished
+//    cell and intake of the next, (A) step-attempt setup, (B) the wave-wide
+//    factorization pass, (C) one right-hand side, (D) the Newton /
 //    error-test / step-control logic.  Every heavy routine has one call site,
 //    so cells in different phases still share the RHS and solve instructions.
+#pragma once
 
 #include "burn_internal.h"
 
@@ -41,7 +44,10 @@ constexpr double kMaxFactor = 10.0;
 constexpr double kNewtonTol = 0.03;
 constexpr int kNewtonMaxIt = 4;
 
-enum { PH_F0 = 0, PH_F1 = 1, PH_NEWTON = 2, PH_DONE = 3 };
+// per-cell phases: the two initial-step RHS, Newton iterations, finished
+// (outputs pending), waiting for a cell, no more cells
+enum { PH_F0 = 0, PH_F1 = 1, PH_NEWTON = 2, PH_DONE = 3, PH_LOAD = 4, PH_IDLE = 5 };
+enum { ST_OK = 0, ST_MAX_STEPS = 1, ST_UNDERFLOW = 2, ST_NONFINITE = 3, ST_BAD_INPUT = 4 };
 enum { CNT_STEPS = 0, CNT_REJ, CNT_NFAIL, CNT_RHS, CNT_JAC, CNT_LU, CNT_SOLVE, CNT_ORDER };
 
 // gamma_k = sum_{j=1..k} 1/j, summed in ascending j.
@@ -81,6 +87,13 @@ __device__ __forceinline__ int dpp_i32(int v) {
   return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
 // broadcast lane SRC (static) of each aligned group of G lanes
 template <int G, int SRC>
 __device__ __forceinline__ double gbcast(double v) {
@@ -88,6 +101,11 @@ __device__ __forceinline__ double gbcast(double v) {
     return v;
   } else if constexpr (G == 4) {
     return dpp_f64<SRC | (SRC << 2) | (SRC << 4) | (SRC << 6)>(v);
+  } else if constexpr (G == 64) {
+    return readlane_f64(v, SRC);
+  } else if constexpr (G == 32) {
+    const double lo = readlane_f64(v, SRC), hi = readlane_f64(v, SRC + 32);
+    return (__lane_id() & 32) ? hi : lo;
   } else {
     return __shfl(v, SRC, G);
   }
@@ -199,30 +217,25 @@ struct Unroll<0> {
   __device__ __forceinline__ static void run(F &&) {}
 };
 
-}  // namespace
+
 
 // ---------------------------------------------------------------------------
-// LDS layout.  Per workgroup (doubles, then ints, then bytes):
-//   rtab[R*8] emult[R] q[R] qcv[R] roww[nnz] |
-//   rsp[4R] rowoff[N+1] rowr[nnz] coloff[N+1] colent[nsl] | nu8[N*R] | pad
-//   rout[8R] (ints)
-// Per wave: D[CPW][DS] ybuf[CPW][YS] facc[CPW][YS] fbuf[FC][FB] fsc[FC][4]
-// with FB = NP + NP*MS + 2*NP + 1 doubles per factorization slot: y_J (later
-// the pivot row), the Newton matrix with row stride MS (later the factors in
-// position order) and two auxiliary rows.  The per-cell strides DS and YS are
-// 4 doubles more than a multiple of 16 and the matrix row stride MS is odd, so
-// the cells of a wave (and the rows of a matrix) fall in different LDS banks.
+// LDS layout.  Per workgroup, the network tables (ints first, so that the
+// 16-byte loads of a reaction's output list are aligned):
+//   rout[8R] rsp[4R] (ints) | rtab[8R] emult[R] q[R] qcv[R] (doubles)
+// then one area per wave:
+//   D[CPW][DS] ybuf[CPW][YS] facc[CPW][YS] fslot[FC][FB] fsc[FC][4]
+// with FB = NP + n*MS + 2*NP + 1 doubles per factorization slot: y_J, the
+// Newton matrix (n rows, odd row stride MS, later the factors in place) and
+// two auxiliary rows (reciprocal pivots and row indices by position).  The
+// per-cell strides DS and YS are 4 doubles more than a multiple of 16 and MS
+// is odd, so the cells of a wave (and the rows of a matrix) fall in different
+// LDS banks.
 // ---------------------------------------------------------------------------
 
-struct TabSizes {
-  int N, R, nnz, nsl;
-  __host__ __device__ size_t doubles() const {
-    const size_t d = 8 * (size_t)R + 3 * (size_t)R + nnz;
-    const size_t i = 4 * (size_t)R + (N + 1) + nnz + (N + 1) + nsl + 8 * (size_t)R;
-    const size_t b = (size_t)N * R;
-    return d + (i + 1) / 2 + (b + 7) / 8;
-  }
-};
+__host__ __device__ inline size_t tab_doubles_of(int R) { return 17 * (size_t)R; }
+
+__host__ __device__ inline int mat_stride(int n) { return n | 1; }
 
 template <int L, int S>
 struct Shape {
@@ -233,78 +246,85 @@ struct Shape {
   static_assert(NP == 4 || NP == 8 || NP == 16 || NP == 32 || NP == 64, "NP must be a power of 2");
   static constexpr int DS = DROWS * NP + 4;  // history stride per cell
   static constexpr int YS = NP + 4;          // exchange-vector stride per cell
-  static constexpr int MS = NP + 1;          // matrix row stride
-  __host__ __device__ static size_t fb(int) { return (size_t)NP * MS + 3 * NP + 1; }
-  __host__ __device__ static size_t wave_doubles(int R) {
-    return (size_t)CPW * DS + 2 * (size_t)CPW * YS + FC * fb(R) + 4 * FC;
+  __host__ __device__ static size_t fb(int n) {
+    return (size_t)NP + (size_t)n * mat_stride(n) + 2 * (size_t)NP + 1;
+  }
+  __host__ __device__ static size_t wave_doubles(int n) {
+    return (size_t)CPW * DS + 2 * (size_t)CPW * YS + FC * fb(n) + 4 * FC;
   }
 };
 
-template <int L, int S, int W>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
-burn_plain_kernel(BurnArgs a, int block_waves) {
+struct Tabs {
+  const double *rtab, *emult, *q, *qcv;
+  const int *rsp, *rout;
+};
+
+__device__ __forceinline__ Tabs tabs_at(double *smem, int R) {
+  Tabs t;
+  t.rout = reinterpret_cast<const int *>(smem);
+  t.rsp = t.rout + 8 * R;
+  t.rtab = reinterpret_cast<const double *>(t.rsp + 4 * R);
+  t.emult = t.rtab + 8 * (size_t)R;
+  t.q = t.emult + R;
+  t.qcv = t.q + R;
+  return t;
+}
+
+// Copy a network's tables into LDS (all threads of the workgroup take part;
+// the caller synchronizes).
+__device__ __forceinline__ void load_tables(const NetTables &nt, const double *log_mult,
+                                            double *smem) {
+  const int R = nt.R;
+  int *rout = reinterpret_cast<int *>(smem);
+  int *rsp = rout + 8 * R;
+  double *rtab = reinterpret_cast<double *>(rsp + 4 * R);
+  double *emult = rtab + 8 * (size_t)R;
+  double *q = emult + R;
+  double *qcv = q + R;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int i = tid; i < 8 * R; i += nth) {
+    rtab[i] = nt.rtab[i];
+    rout[i] = nt.rout[i];
+  }
+  for (int i = tid; i < R; i += nth) {
+    emult[i] = log_mult ? exp(log_mult[i]) : 1.0;
+    q[i] = nt.q[i];
+    qcv[i] = nt.q[i] * nt.inv_cv;
+  }
+  for (int i = tid; i < 4 * R; i += nth) rsp[i] = nt.rsp[i];
+}
+
+// Burn cells with one wave.  The cells come either from a static map (cell
+// first_cell for this lane group, then nothing) or, when queue is not null,
+// from a device work queue: a group whose cell has finished writes it out and
+// takes the next index from the queue, until the queue passes n_cells.  The
+// loop ends when every group of the wave is idle.
+template <int L, int S, bool QUEUE>
+__device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, double *wb,
+                                          int64_t first_cell, unsigned long long *queue) {
   using SH = Shape<L, S>;
   constexpr int NP = SH::NP, CPW = SH::CPW, FL = SH::FL, FC = SH::FC;
-  constexpr int DS = SH::DS, YS = SH::YS, MS = SH::MS;
-  extern __shared__ double smem[];
+  constexpr int DS = SH::DS, YS = SH::YS;
 
   const NetTables &nt = a.net;
-  const int N = nt.N, R = nt.R, n = nt.n, nnz = nt.nnz, nsl = nt.nsl;
-  const TabSizes ts{N, R, nnz, nsl};
+  const int N = nt.N, R = nt.R, n = nt.n;
+  const int MS = mat_stride(n);
+  const size_t FB = SH::fb(n);
 
-  // ---- workgroup tables
-  double *s_rtab = smem;
-  double *s_emult = s_rtab + 8 * (size_t)R;
-  double *s_q = s_emult + R;
-  double *s_qcv = s_q + R;
-  double *s_roww = s_qcv + R;
-  int *s_rsp = reinterpret_cast<int *>(s_roww + nnz);
-  int *s_rowoff = s_rsp + 4 * R;
-  int *s_rowr = s_rowoff + N + 1;
-  int *s_coloff = s_rowr + nnz;
-  int *s_colent = s_coloff + N + 1;
-  int *s_rout = s_colent + nsl;
-  signed char *s_nu = reinterpret_cast<signed char *>(s_rout + 8 * R);
-  {
-    const int tid = threadIdx.x, nth = blockDim.x;
-    for (int i = tid; i < 8 * R; i += nth) s_rtab[i] = nt.rtab[i];
-    for (int i = tid; i < R; i += nth) {
-      s_emult[i] = a.log_mult ? exp(a.log_mult[i]) : 1.0;
-      s_q[i] = nt.q[i];
-      s_qcv[i] = nt.q[i] * nt.inv_cv;
-    }
-    for (int i = tid; i < nnz; i += nth) {
-      s_roww[i] = nt.row_w[i];
-      s_rowr[i] = nt.row_r[i];
-    }
-    for (int i = tid; i < 4 * R; i += nth) s_rsp[i] = nt.rsp[i];
-    for (int i = tid; i <= N; i += nth) {
-      s_rowoff[i] = nt.row_off[i];
-      s_coloff[i] = nt.col_off[i];
-    }
-    for (int i = tid; i < nsl; i += nth) s_colent[i] = nt.col_ent[i];
-    for (int i = tid; i < 8 * R; i += nth) s_rout[i] = nt.rout[i];
-    for (int i = tid; i < N * R; i += nth) s_nu[i] = nt.nu8[i];
-  }
-  __syncthreads();
-
-  const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int q = lane % L;
   const int cw = lane / L;
   const int64_t C = a.n_cells;
-  const int64_t cell = ((int64_t)blockIdx.x * block_waves + wave) * CPW + cw;
-  const bool in_range = cell < C;
 
-  double *wb = smem + ts.doubles() + (size_t)wave * SH::wave_doubles(R);
   double *Dl = wb + (size_t)cw * DS;  // this cell's history, [DROWS][NP]
   double *ybuf = wb + (size_t)CPW * DS + (size_t)cw * YS;
   double *facc = wb + (size_t)CPW * DS + (size_t)CPW * YS + (size_t)cw * YS;
   double *fbase = wb + (size_t)CPW * DS + 2 * (size_t)CPW * YS;
-  double *fsc = fbase + (size_t)FC * SH::fb(R);
+  double *fsc = fbase + (size_t)FC * FB;
 
   const double rtol = a.rtol, atol = a.atol, t_end = a.t_end;
-  const double rho = in_range ? a.rho[cell] : 1.0;
+  const double *s_rtab = tb.rtab, *s_emult = tb.emult, *s_q = tb.q, *s_qcv = tb.qcv;
+  const int *s_rsp = tb.rsp, *s_rout = tb.rout;
 
   // ---- per-lane state (group layout)
   double LU[S][NP];  // factor rows held at positions s*L+q
@@ -368,6 +388,8 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       }
     }
   };
+
+  double rho = 1.0;
 
   // ---- right-hand side F = f(yv) for the own components; 1 if finite.
   // The group's lanes take the reactions r = q, q+L, ...; each rate is added
@@ -456,13 +478,50 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
   };
 
   // ================= cell state machine =================
-  int phase = in_range ? PH_F0 : PH_DONE;
+  int64_t cell = -1;
+  int phase = PH_LOAD;
   int status = 0, write_state = 0;
   int k = 1, n_eq = 0, jac_cur = 0, lu_ok = 0, it = 0, need_attempt = 0, new_step = 0;
   int fresh_newton = 0, first_jac = 0;
   double t = 0.0, h = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, err = 0.0, h0 = 0.0, d1 = 0.0;
 
-  if (in_range) {
+  // outputs of the group's cell: state (if integration started), status and
+  // counters
+  auto write_out = [&]() __attribute__((always_inline)) {
+    if (write_state) {
+      cnt[CNT_ORDER] = k;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const int i = comp(s);
+        if (i < N) a.Y[(int64_t)i * C + cell] = Dl[i];
+        else if (i == N) a.T[cell] = Dl[i];
+      }
+    }
+    if (q == 0) {
+      if (a.status) a.status[cell] = status;
+      if (a.counters) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          a.counters[(int64_t)c * C + cell] = (status == ST_BAD_INPUT) ? 0 : cnt[c];
+      }
+    }
+  };
+
+  // take cell c (or go idle if c >= C): load its state and check the inputs
+  auto load_cell = [&](int64_t c) __attribute__((always_inline)) {
+    if (c >= C) {
+      phase = PH_IDLE;
+      return;
+    }
+    cell = c;
+    rho = a.rho[cell];
+    status = 0;
+    write_state = 0;
+    k = 1;
+    n_eq = jac_cur = lu_ok = it = need_attempt = new_step = fresh_newton = first_jac = 0;
+    t = h = t_new = cc = dprev = err = h0 = d1 = 0.0;
+#pragma unroll
+    for (int c8 = 0; c8 < 8; ++c8) cnt[c8] = 0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int i = comp(s);
@@ -476,12 +535,40 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       if (i == N && !(yv[s] > 0.0)) bad = 1;
     }
     if (gor<L>(bad)) {
-      status = 4;
+      status = ST_BAD_INPUT;
       phase = PH_DONE;
+    } else {
+      phase = PH_F0;
     }
-  }
+  };
+  if constexpr (!QUEUE) load_cell(first_cell);
 
   while (true) {
+    // ---------------- 0: write a finished cell, take the next one ----------------
+    if constexpr (QUEUE) {
+      if (phase == PH_DONE) {
+        write_out();
+        phase = PH_LOAD;
+      }
+    }
+    if constexpr (QUEUE) {
+      const unsigned long long lmask = __ballot(phase == PH_LOAD && q == 0);
+      if (lmask) {
+        // one atomic per wave; the requesting groups take consecutive indices
+        const int leader = __ffsll((long long)lmask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(queue, (unsigned long long)__popcll(lmask));
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(base & 0xffffffffULL), leader);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(base >> 32), leader);
+        base = ((unsigned long long)hi << 32) | lo;
+        const unsigned long long below = lmask & ((1ULL << (cw * L)) - 1ULL);
+        const unsigned long long idx = base + (unsigned long long)__popcll(below);
+        if (phase == PH_LOAD) load_cell(idx < (unsigned long long)C ? (int64_t)idx : C);
+      }
+    }
+    // static map: a finished cell stays done and is written after the loop
+    if (__ballot(phase != PH_IDLE && (QUEUE || phase != PH_DONE)) == 0) break;
+
     // ---------------- A: start of a step attempt ----------------
     if (phase == PH_NEWTON && need_attempt) {
       if (new_step && cnt[CNT_STEPS] >= a.max_steps) {
@@ -560,7 +647,7 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       for (int j = 0; j < FC; ++j)
         if (sel[j] == cw) myslot = j;
       if (myslot >= 0) {
-        double *py = fbase + (size_t)myslot * SH::fb(R);
+        double *py = fbase + (size_t)myslot * FB;
 #pragma unroll
         for (int s = 0; s < S; ++s) py[comp(s)] = yJ[s];
         if (q == 0) {
@@ -569,18 +656,24 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
         }
       }
       wave_lds_sync();
-      // (b) factor layout: slot fj = lane / FL, row fi = lane % FL
+      // (b) factor layout: slot fj = lane / FL, row fi = lane % FL; the rows
+      // fi >= n of a padded system take no part
       const int fj = lane / FL, fi = lane % FL;
       int fsel = -1;
 #pragma unroll
       for (int j = 0; j < FC; ++j)
         if (j == fj) fsel = sel[j];
-      double *fy = fbase + (size_t)fj * SH::fb(R);
-      double *fM = fy + NP;  // Newton matrix [NP][MS], row-major
+      double *fy = fbase + (size_t)fj * FB;
+      double *fM = fy + NP;  // Newton matrix [n][MS], row-major
       const double fcc = fsel >= 0 ? fsc[4 * fj + 0] : 0.0;
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
+      const bool frow = fi < n;
+      if (frow) {
+        double *mr = fM + fi * MS;
 #pragma unroll
-      for (int j = 0; j < NP; ++j) fM[fi * MS + j] = (fi == j) ? 1.0 : 0.0;
+        for (int j = 0; j < NP; ++j)
+          if (j < n) mr[j] = (fi == j) ? 1.0 : 0.0;
+      }
       wave_lds_sync();
       // Rates at y_J for the reactions r = fi, fi+FL, ...; every Jacobian term
       // W(i, r) dR_r/dy_j (W = nu for a species row, q/c_v for the temperature
@@ -650,28 +743,31 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       int pos = fi;
       int fsing = 0;
       double fdinv = 1.0;
-      double *Mrow = fM + fi * MS;
+      double *Mrow = fM + (frow ? fi : 0) * MS;
       for (int K = 0; K < n; ++K) {
         double v = -2.0;
         int nan_k = 0;
-        if (pos >= K) {
+        const bool cand = frow && pos >= K;
+        if (cand) {
           v = fabs(Mrow[K]);
           if (v != v) {
             if (pos == K) nan_k = 1;
             v = -1.0;
           }
         }
-        int bp = (pos >= K) ? pos : (1 << 30);
+        int bp = cand ? pos : (1 << 30);
         int prow_i = fi;  // physical row of the pivot (payload of the arg-max)
         gargmax3<FL>(v, bp, prow_i);
         nan_k = gor<FL>(nan_k);
         if (!(v > 0.0) || nan_k) fsing = 1;
-        if (pos == K) pos = bp;
-        else if (pos == bp) pos = K;
+        if (frow) {
+          if (pos == K) pos = bp;
+          else if (pos == bp) pos = K;
+        }
         const double *P = fM + prow_i * MS;
         const double rinv = 1.0 / P[K];
-        if (pos == K) fdinv = rinv;
-        if (pos > K) {
+        if (frow && pos == K) fdinv = rinv;
+        if (frow && pos > K) {
           const double l = Mrow[K] * rinv;
           Mrow[K] = l;
           for (int j = K + 1; j < n; ++j) Mrow[j] -= l * P[j];
@@ -679,10 +775,12 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
         wave_lds_sync();
       }
       // (d) the factors stay in LDS; publish position -> row and 1/U_pp
-      double *aux = fM + NP * MS;
+      double *aux = fM + (size_t)n * MS;
       if (fsel >= 0) {
-        aux[pos] = fdinv;
-        aux[NP + pos] = (double)fi;
+        if (frow) {
+          aux[pos] = fdinv;
+          aux[NP + pos] = (double)fi;
+        }
         if (fi == 0) {
           fsc[4 * fj + 2] = (double)fsing;
           fsc[4 * fj + 3] = (double)jbad;
@@ -690,15 +788,25 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       }
       wave_lds_sync();
       if (myslot >= 0) {
-        const double *src = fbase + (size_t)myslot * SH::fb(R) + NP;
+        const double *src = fbase + (size_t)myslot * FB + NP;
+        const double *saux = src + (size_t)n * MS;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int p = comp(s);
-          dinv[s] = src[NP * MS + p];
-          ridx[s] = (int)src[NP * MS + NP + p];
-          const double *row = src + ridx[s] * MS;
+          if (p < n) {
+            // entries j >= n of a row are never used by the solves; reading
+            // them stays inside this slot (the auxiliary rows follow)
+            dinv[s] = saux[p];
+            ridx[s] = (int)saux[NP + p];
+            const double *row = src + ridx[s] * MS;
 #pragma unroll
-          for (int j = 0; j < NP; ++j) LU[s][j] = row[j];
+            for (int j = 0; j < NP; ++j) LU[s][j] = row[j];
+          } else {
+            dinv[s] = 1.0;
+            ridx[s] = p;
+#pragma unroll
+            for (int j = 0; j < NP; ++j) LU[s][j] = 0.0;
+          }
         }
         sing = fsc[4 * myslot + 2] != 0.0;
         if (first_jac && fsc[4 * myslot + 3] != 0.0) {
@@ -721,7 +829,7 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
     fresh_newton = 0;
 
     // ---------------- C: right-hand side ----------------
-    const int do_rhs = (phase != PH_DONE) && !nfail;
+    const int do_rhs = (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail;
     int okf = 1;
     if (do_rhs) {
       okf = rhs();
@@ -931,89 +1039,11 @@ burn_plain_kernel(BurnArgs a, int block_waves) {
       }
     }
     if (pend != 0.0 && phase == PH_NEWTON) rescale(k, pend);
-
-    if (__ballot(phase != PH_DONE) == 0) break;
   }
-  if (write_state) cnt[CNT_ORDER] = k;
-
-  // ---- outputs
-  if (in_range) {
-    if (write_state) {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const int i = comp(s);
-        if (i < N) a.Y[(int64_t)i * C + cell] = Dl[i];
-        else if (i == N) a.T[cell] = Dl[i];
-      }
-    }
-    if (q == 0) {
-      if (a.status) a.status[cell] = status;
-      if (a.counters) {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) a.counters[(int64_t)c * C + cell] = (status == 4) ? 0 : cnt[c];
-      }
-    }
+  if constexpr (!QUEUE) {
+    if (phase == PH_DONE) write_out();
   }
 }
 
-// ---------------------------------------------------------------------------
-
-bool choose_shape(int n, int lanes_hint, int *L, int *S) {
-  struct Sh {
-    int L, S;
-  };
-  static const Sh shapes[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {16, 4}};
-  for (const Sh &sh : shapes) {
-    if (lanes_hint && sh.L != lanes_hint) continue;
-    if (sh.L * sh.S >= n) {
-      *L = sh.L;
-      *S = sh.S;
-      return true;
-    }
-  }
-  return false;
-}
-
-template <int L, int S>
-static size_t lds_bytes_t(const BurnArgs &a, int block_waves) {
-  const TabSizes ts{a.net.N, a.net.R, a.net.nnz, a.net.nsl};
-  return 8 * (ts.doubles() + (size_t)block_waves * Shape<L, S>::wave_doubles(a.net.R));
-}
-
-template <int L, int S, int W>
-static hipError_t launch_one(const BurnArgs &a, int block_waves, hipStream_t stream) {
-  constexpr int CPW = 64 / L;
-  const size_t lds = lds_bytes_t<L, S>(a, block_waves);
-  const int64_t cells_per_block = (int64_t)CPW * block_waves;
-  const int64_t blocks = (a.n_cells + cells_per_block - 1) / cells_per_block;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((burn_plain_kernel<L, S, W>), dim3((unsigned)blocks), dim3(64 * block_waves),
-                     lds, stream, a, block_waves);
-  return hipGetLastError();
-}
-
-size_t plain_lds_bytes(const BurnArgs &a, int L, int S, int block_waves) {
-#define BN_CASE(l, s) \
-  if (L == l && S == s) return lds_bytes_t<l, s>(a, block_waves);
-  BN_CASE(4, 1)
-  BN_CASE(4, 2)
-  BN_CASE(4, 4)
-  BN_CASE(8, 4)
-  BN_CASE(16, 4)
-#undef BN_CASE
-  return (size_t)-1;
-}
-
-hipError_t launch_plain(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
-#define BN_CASE(l, s, w) \
-  if (L == l && S == s) return launch_one<l, s, w>(a, block_waves, stream);
-  BN_CASE(4, 1, 2)
-  BN_CASE(4, 2, 2)
-  BN_CASE(4, 4, 1)
-  BN_CASE(8, 4, 1)
-  BN_CASE(16, 4, 1)
-#undef BN_CASE
-  return hipErrorInvalidValue;
-}
-
+}  // namespace
 }  // namespace bn

@@ -44,11 +44,42 @@ struct BurnArgs {
   int max_steps;
 };
 
-// Kernel variants: lanes per cell L and slots per lane S (system padded to
-// L*S components).  Returns hipSuccess or the launch error.
+// Shapes (lanes per cell L, slots per lane S; the system is padded to
+// NP = L*S components).  Plain kernels exist for every shape below; the
+// persistent multi-network kernel for the MULTI_SHAPES subset.
+struct ShapeLS {
+  int L, S;
+};
+constexpr ShapeLS PLAIN_SHAPES[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {16, 2},
+                                    {32, 1}, {16, 4}, {32, 2}, {64, 1}};
+constexpr int N_PLAIN_SHAPES = 9;
+constexpr ShapeLS MULTI_SHAPES[] = {{4, 4}, {16, 2}, {32, 1}, {64, 1}};
+constexpr int N_MULTI_SHAPES = 4;
+
+// LDS bytes of the network tables and of one wave's working area.
+size_t table_lds_bytes(int R);
+size_t wave_lds_bytes(int L, int S, int n);
+
+// One launch of the plain kernel: cells map statically to lane groups.
 hipError_t launch_plain(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 
-// Choose (L, S) for a system of size n; returns false if unsupported.
-bool choose_shape(int n, int lanes_hint, int *L, int *S);
+// The persistent multi-network launch: every workgroup walks the items in
+// order, and its waves take cells of the current item from that item's
+// device queue counter until it passes n_cells.
+constexpr int MAX_ITEMS = 8;
+struct MultiArgs {
+  BurnArgs item[MAX_ITEMS];
+  int shape[MAX_ITEMS];           // index into MULTI_SHAPES
+  unsigned long long *queue;      // [n_items] counters, zeroed before the launch
+  int n_items;
+  int block_waves;
+  size_t tab_doubles;             // LDS doubles reserved for tables (max over items)
+  size_t wave_doubles;            // LDS doubles per wave area (max over items)
+};
+hipError_t launch_multi(const MultiArgs &m, int grid, hipStream_t stream);
+
+// Zero n counters with a kernel (no memset node, so the sequence can be
+// captured into a graph and replayed).
+hipError_t launch_zero(unsigned long long *p, int n, hipStream_t stream);
 
 }  // namespace bn

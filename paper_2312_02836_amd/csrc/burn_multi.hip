@@ -1,0 +1,110 @@
+// burn_multi.hip -- the persistent multi-network kernel, the counter reset
+// kernel, and the host-side shape dispatch and LDS sizing for all kernels.
+//
+// Persistent scheduling: the grid is sized to the machine (one or a few
+// workgroups per compute unit), not to the work.  Every workgroup walks the
+// batch items in the order given (the host puts the costliest cells first);
+// for each item it loads the network's tables into LDS once, and its waves
+// then take cells from the item's queue counter, one lane group at a time,
+// until the counter passes the item's cell count.  A group that finishes a
+// cell early takes the next one at once, so cells of uneven stiffness do not
+// leave lanes idle until the slowest cell of a static batch is done, and the
+// tails of the different networks overlap instead of adding up.
+
+#include "burn_body.h"
+
+namespace bn {
+
+hipError_t launch_plain_p0(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream,
+                           bool *found);
+hipError_t launch_plain_p1(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream,
+                           bool *found);
+hipError_t launch_plain_p2(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream,
+                           bool *found);
+
+namespace {
+
+template <int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
+burn_multi_kernel(MultiArgs m) {
+  extern __shared__ double smem[];
+  __shared__ int s_skip;
+  const int wave = threadIdx.x >> 6;
+  double *wb = smem + m.tab_doubles + (size_t)wave * m.wave_doubles;
+  for (int j = 0; j < m.n_items; ++j) {
+    const BurnArgs &a = m.item[j];
+    // An item whose queue has already run out is skipped without loading.
+    if (threadIdx.x == 0)
+      s_skip = __hip_atomic_load(&m.queue[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+               (unsigned long long)a.n_cells;
+    __syncthreads();  // every wave is done with the previous item's tables
+    const int skip = s_skip;
+    if (!skip) load_tables(a.net, a.log_mult, smem);
+    __syncthreads();
+    if (skip) continue;
+    const Tabs tb = tabs_at(smem, a.net.R);
+    unsigned long long *qj = m.queue + j;
+    switch (m.shape[j]) {
+      case 0: run_cells<4, 4, true>(a, tb, wb, 0, qj); break;
+      case 1: run_cells<16, 2, true>(a, tb, wb, 0, qj); break;
+      case 2: run_cells<32, 1, true>(a, tb, wb, 0, qj); break;
+      default: run_cells<64, 1, true>(a, tb, wb, 0, qj); break;
+    }
+  }
+}
+
+__global__ void zero_kernel(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ULL;
+}
+
+template <int L, int S>
+size_t wave_doubles_t(int n) {
+  return Shape<L, S>::wave_doubles(n);
+}
+
+}  // namespace
+
+size_t table_lds_bytes(int R) { return 8 * tab_doubles_of(R); }
+
+size_t wave_lds_bytes(int L, int S, int n) {
+#define BN_W(l, s) \
+  if (L == l && S == s) return 8 * wave_doubles_t<l, s>(n);
+  BN_W(4, 1)
+  BN_W(4, 2)
+  BN_W(4, 4)
+  BN_W(8, 4)
+  BN_W(16, 2)
+  BN_W(32, 1)
+  BN_W(16, 4)
+  BN_W(32, 2)
+  BN_W(64, 1)
+#undef BN_W
+  return (size_t)-1;
+}
+
+hipError_t launch_plain(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
+  bool found = false;
+  hipError_t e = launch_plain_p0(a, L, S, block_waves, stream, &found);
+  if (found) return e;
+  e = launch_plain_p1(a, L, S, block_waves, stream, &found);
+  if (found) return e;
+  e = launch_plain_p2(a, L, S, block_waves, stream, &found);
+  if (found) return e;
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_multi(const MultiArgs &m, int grid, hipStream_t stream) {
+  const size_t lds = 8 * (m.tab_doubles + (size_t)m.block_waves * m.wave_doubles);
+  hipLaunchKernelGGL((burn_multi_kernel<1>), dim3((unsigned)grid), dim3(64 * m.block_waves), lds,
+                     stream, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(unsigned long long *p, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace bn

@@ -282,17 +282,62 @@ def _candidates(mass: np.ndarray) -> Dict[str, List[Tuple[Tuple[int, ...], Tuple
     return out
 
 
+def _touched(chosen) -> set:
+    out = set()
+    for rs, ps in chosen:
+        out.update(rs)
+        out.update(ps)
+    return out
+
+
+def _ensure_seed_reactions(rng, mass, chosen, pools, k_min):
+    """Replace reactions until at least k_min have only seed reactants; None
+    if that cannot be done while every species stays in some reaction."""
+    seeds = set(np.argsort(_potentials(mass), kind="stable")[:3].tolist())
+
+    def seed_only(rx):
+        return all(s in seeds for s in rx[0])
+
+    have = sum(seed_only(c) for c in chosen)
+    if have >= k_min:
+        return chosen
+    n_species = len(mass)
+    pool = [c for pl in pools for c in pl if seed_only(c) and c not in chosen]
+    need = min(k_min - have, len(pool))
+    if need <= 0:
+        return chosen
+    picks = sorted(rng.choice(len(pool), size=need, replace=False).tolist())
+    chosen = list(chosen)
+    for i in picks:
+        new = pool[i]
+        for idx in rng.permutation(len(chosen)).tolist():
+            if seed_only(chosen[idx]):
+                continue
+            trial = chosen[:idx] + chosen[idx + 1:] + [new]
+            if len(_touched(trial)) == n_species:
+                chosen = trial
+                break
+        else:
+            return None
+    return chosen
+
+
 def random_network(seed: int, n_species: int, n_reactions: int, *, name: Optional[str] = None,
                    mix: Tuple[float, float, float] = (0.20, 0.65, 0.15),
                    t_window: Tuple[float, float] = (1.0, 5.0),
                    lam_window: Tuple[float, float] = (1e-6, 1e8),
-                   c_v: float = 100.0) -> NetworkSpec:
+                   c_v: float = 100.0, min_seed_reactions: int = 3) -> NetworkSpec:
     """Seeded acyclic mass-action network with 1-, 2- and 3-body reactions.
 
     mix = fractions of (1-body, 2-body, 3-body) reactions; 2-body reactions
     are captures a+b->c and exchanges a+b->c+d.  Every reaction conserves mass
     number and raises the species potential (no cycles, bounded heating).
     Every species takes part in at least one reaction; no duplicates.
+    At least min_seed_reactions reactions have only seed species (the three
+    of lowest potential, which start the burn) as reactants, so that a burn
+    from a seed composition is not trivially inert: a network drawn without
+    enough of them has randomly chosen other reactions replaced by seed-only
+    candidates (networks that already have enough are left as drawn).
     a1..a6 are drawn small and a0 is placed so every rate lies in lam_window
     over t_window.  q_r ~ U[0,5]; c_v constant.
     """
@@ -316,11 +361,10 @@ def random_network(seed: int, n_species: int, n_reactions: int, *, name: Optiona
             if want[k]:
                 idx = rng.choice(len(pools[k]), size=want[k], replace=False)
                 chosen += [pools[k][i] for i in sorted(idx)]
-        touched = set()
-        for rs, ps in chosen:
-            touched.update(rs)
-            touched.update(ps)
-        if len(touched) != n_species:
+        if len(_touched(chosen)) != n_species:
+            continue
+        chosen = _ensure_seed_reactions(rng, mass, chosen, pools, min_seed_reactions)
+        if chosen is None:
             continue
         break
     else:

@@ -20,6 +20,8 @@ def compare(Yg, Tg, stg, cntg, Yo, To, sto, cnto, rtol, atol):
     same_cnt = np.all(np.asarray(cntg) == np.asarray(cnto), axis=0)
     per_cell = ewt.max(axis=0) if ewt.size else np.zeros(0)
     return {
+        "per_cell_ewt": per_cell,
+        "same_counters": same_cnt,
         "n_cells": int(yo.shape[1]),
         "status_equal": bool(np.array_equal(np.asarray(stg), np.asarray(sto))),
         "max_ewt": float(per_cell.max()) if per_cell.size else 0.0,
@@ -35,3 +37,45 @@ def summary(rep) -> str:
             f"max_ewt={rep['max_ewt']:.3e} violations={rep['n_violations']} "
             f"counters_equal={rep['counter_equal_frac']:.5f} "
             f"max_ewt(same counters)={rep['max_ewt_same_counters']:.3e}")
+
+
+# Global-error bound the oracle itself is pinned to (its rtol-1e-6 solutions
+# lie within 100 (rtol |y| + atol) of closed forms and tight references).
+GLOBAL_ERROR_BOUND = 100.0
+
+
+def assert_parity(g, o, rtol, atol, *, min_counter_equal=0.99, tight=None):
+    """The parity gate.
+
+    * statuses equal for every cell;
+    * cells whose eight counters equal the oracle's (same sequence of step,
+      order and Newton decisions) must match it within rtol |y| + atol per
+      component;
+    * at most 1 - min_counter_equal of the cells may have taken a different
+      decision sequence (a rounding-level difference can flip one accept /
+      reject or order choice; both are then valid BDF solutions).  Each such
+      cell that misses the per-component bound must still be a valid
+      solution: ``tight(idx)`` returns the oracle's (Y, T) for those cells at
+      a tolerance 1e4 times tighter, and the GPU result must lie within the
+      oracle's pinned global-error bound of it.
+    """
+    rep = compare(*g, *o, rtol, atol)
+    print(summary(rep), flush=True)
+    assert rep["status_equal"], "per-cell status differs"
+    assert rep["counter_equal_frac"] >= min_counter_equal, summary(rep)
+    ewt, same = rep["per_cell_ewt"], rep["same_counters"]
+    bad_same = np.nonzero((ewt > 1.0) & same)[0]
+    assert bad_same.size == 0, ("cells with the oracle's decisions off by more than the "
+                                "tolerance", bad_same[:10], summary(rep))
+    bad_div = np.nonzero((ewt > 1.0) & ~same)[0]
+    if bad_div.size:
+        assert tight is not None, ("counter-divergent cells off by more than the tolerance",
+                                   bad_div[:10], summary(rep))
+        Yt, Tt = tight(bad_div)
+        yt = stack_state(Yt, Tt)
+        yg = stack_state(np.asarray(g[0])[:, bad_div], np.asarray(g[1])[bad_div])
+        err = (np.abs(yg - yt) / (rtol * np.abs(yt) + atol)).max(axis=0)
+        print(f"divergent cells {bad_div.tolist()[:10]}: error vs tight reference "
+              f"{err.max():.3e} (bound {GLOBAL_ERROR_BOUND})", flush=True)
+        assert np.all(err <= GLOBAL_ERROR_BOUND), (bad_div, err)
+    return rep

@@ -94,3 +94,31 @@ def test_burn_rejects_bad_arguments_on_host(L):
                         None) == _lib.BN_EINVAL
     L.bn_network_destroy(None)  # no-op
     assert L.bn_network_n_species(None) == -1
+
+
+def test_multi_and_tuning_reject_bad_arguments_on_host(L):
+    """Argument checks of the persistent and tuning entry points that come
+    before any device call."""
+    from paper_2312_02836_amd import _lib
+    opts = _lib.BurnOpts(0, 0, 0, 0)
+    items = (_lib.BatchItem * 1)()
+    assert L.burn_batch_multi(-1, items, 1e-2, 1e-6, 1e-10, None, None, 0, None) == _lib.BN_EINVAL
+    assert L.burn_batch_multi(9, items, 1e-2, 1e-6, 1e-10, None, None, 0, None) == _lib.BN_EINVAL
+    assert L.burn_batch_multi(1, None, 1e-2, 1e-6, 1e-10, None, None, 0, None) == _lib.BN_EINVAL
+    assert L.burn_batch_multi(1, items, 0.0, 1e-6, 1e-10, None, None, 0, None) == _lib.BN_EINVAL
+    assert L.burn_batch_multi(1, items, 1e-2, 1e-6, -1.0, None, None, 0, None) == _lib.BN_EINVAL
+    bad = _lib.BurnOpts(0, 4, 0, 0)
+    assert L.burn_batch_multi(1, items, 1e-2, 1e-6, 1e-10, C.byref(bad), None, 0,
+                              None) == _lib.BN_EINVAL
+    assert b"lanes_per_cell" in L.bn_last_error()
+    assert L.burn_batch_multi(0, items, 1e-2, 1e-6, 1e-10, C.byref(opts), None, 0,
+                              None) in (_lib.BN_SUCCESS, _lib.BN_EHIP)
+    assert L.burn_batch_multi_workspace_bytes(1) == 256
+    assert L.burn_batch_multi_workspace_bytes(8) == 256
+    n = C.c_int32(5)
+    assert L.bn_network_autotune(None, 10, None, None, None, 1e-2, 1e-6, 1e-10, None, 0, None,
+                                 0, C.byref(n), None) == _lib.BN_EINVAL
+    assert n.value == 0
+    assert L.bn_network_set_launch(None, 4, 4, 0) == _lib.BN_EINVAL
+    a = C.c_int32()
+    assert L.bn_network_get_launch(None, C.byref(a), C.byref(a), C.byref(a)) == _lib.BN_EINVAL

@@ -1,0 +1,179 @@
+"""The persistent multi-network kernel, the large-network shapes, HIP-graph
+replay and the autotuner, through the C ABI, against the CPU oracle (and,
+bitwise, against the plain kernel with the same launch shape)."""
+import numpy as np
+import pytest
+
+from paper_2312_02836_amd import synth
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-6, 1e-10
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2312_02836_amd import burn as B
+    return B
+
+
+def _host(out):
+    import torch
+    torch.cuda.synchronize()
+    return tuple(x.cpu().numpy() for x in out)
+
+
+def _oracle(oracle, spec, cells, t_end, **kw):
+    return oracle.burn(oracle.OracleNet(spec), cells, t_end, RTOL, ATOL, **kw)
+
+
+def _check(g, oracle, spec, cells, t_end, min_counter_equal=0.99):
+    """Parity with the oracle on the same cells (tests.parity.assert_parity);
+    counter-divergent cells are checked against a 1e4 times tighter oracle
+    solution."""
+    o = _oracle(oracle, spec, cells, t_end)
+
+    def tight(idx):
+        r = oracle.burn(oracle.OracleNet(spec), cells.subset(idx), t_end, RTOL * 1e-4, ATOL * 1e-4)
+        return r[0], r[1]
+
+    return assert_parity(g, o, RTOL, ATOL, min_counter_equal=min_counter_equal, tight=tight)
+
+
+def _mixed(n_cells=(700, 513, 300, 257)):
+    """The four-network mixed workload at small, ragged cell counts."""
+    cfg = synth.config(4, n_cells=max(n_cells))
+    cells = [c.subset(np.arange(k)) for c, k in zip(cfg.cells, n_cells)]
+    return cfg, cells
+
+
+@pytest.mark.parametrize("lanes", [4, 32, 64])
+def test_plain_more_shapes_synth13(gpu, oracle, lanes):
+    cfg = synth.config(2, n_cells=515)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = gpu.Network(spec)
+    g = _host(gpu.burn(net, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL,
+                       lanes_per_cell=lanes))
+    _check(g, oracle, spec, cells, cfg.t_end)
+    net.close()
+
+
+@pytest.mark.parametrize("which", [1, 2, 3])
+def test_plain_large_networks(gpu, oracle, which):
+    """21/60, 35/100 and 50/150 species/reactions with their default shapes."""
+    cfg, cells = _mixed()
+    spec, c = cfg.networks[which], cells[which]
+    net = gpu.Network(spec)
+    print("launch", net.get_launch(), flush=True)
+    g = _host(gpu.burn(net, c.Y, c.rho, c.T, cfg.t_end, RTOL, ATOL))
+    _check(g, oracle, spec, c, cfg.t_end)
+    net.close()
+
+
+def test_multi_mixed_parity_and_bitwise_plain(gpu, oracle):
+    """All four networks in one persistent launch: parity with the oracle,
+    and bitwise equality with plain launches of the same shapes."""
+    cfg, cells = _mixed()
+    nets = [gpu.Network(s) for s in cfg.networks]
+    outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cells)], cfg.t_end,
+                          RTOL, ATOL)
+    multi_shapes = {(4, 4), (16, 2), (32, 1), (64, 1)}
+    for n, spec, c, out in zip(nets, cfg.networks, cells, outs):
+        g = _host(out)
+        print(spec.name, flush=True)
+        _check(g, oracle, spec, c, cfg.t_end)
+        L, S, _ = n.get_launch()
+        if (L, S) in multi_shapes:
+            p = _host(gpu.burn(n, c.Y, c.rho, c.T, cfg.t_end, RTOL, ATOL))
+            for a, b in zip(g, p):
+                assert np.array_equal(a, b, equal_nan=True)
+    for n in nets:
+        n.close()
+
+
+def test_multi_reuse_deterministic_and_empty_item(gpu):
+    import torch
+    cfg, cells = _mixed((300, 200, 0, 130))
+    nets = [gpu.Network(s) for s in cfg.networks]
+    dev = torch.device("cuda", 0)
+    Y0 = [torch.as_tensor(c.Y, device=dev) for c in cells]
+    T0 = [torch.as_tensor(c.T, device=dev) for c in cells]
+    Yw = [y.clone() for y in Y0]
+    Tw = [t.clone() for t in T0]
+    mb = gpu.MultiBurn([(n, y, torch.as_tensor(c.rho, device=dev), t)
+                        for n, y, t, c in zip(nets, Yw, Tw, cells)], cfg.t_end, RTOL, ATOL)
+    mb.run()
+    first = [tuple(x.clone() for x in o[:4]) for o in mb.outputs]
+    for _ in range(2):
+        for y, t, y0, t0 in zip(Yw, Tw, Y0, T0):
+            y.copy_(y0)
+            t.copy_(t0)
+        mb.run()
+        torch.cuda.synchronize()
+        for o, f in zip(mb.outputs, first):
+            for a, b in zip(o[:4], f):
+                assert torch.equal(a, b)
+    assert mb.outputs[2][0].shape == (cfg.networks[2].n_species, 0)
+    assert int((first[0][2] != 0).sum()) == 0 and int((first[3][2] != 0).sum()) == 0
+    for n in nets:
+        n.close()
+
+
+def test_multi_graph_replay(gpu):
+    """Capture the persistent burn into a HIP graph and replay it several
+    times, with eager work and synchronizations between the replays; every
+    replay must equal the eager result bitwise."""
+    import torch
+    cfg, cells = _mixed((257, 130, 129, 64))
+    nets = [gpu.Network(s) for s in cfg.networks]
+    dev = torch.device("cuda", 0)
+    Y0 = [torch.as_tensor(c.Y, device=dev) for c in cells]
+    T0 = [torch.as_tensor(c.T, device=dev) for c in cells]
+    Yw = [y.clone() for y in Y0]
+    Tw = [t.clone() for t in T0]
+    mb = gpu.MultiBurn([(n, y, torch.as_tensor(c.rho, device=dev), t)
+                        for n, y, t, c in zip(nets, Yw, Tw, cells)], cfg.t_end, RTOL, ATOL)
+    mb.run()
+    torch.cuda.synchronize()
+    eager = [tuple(x.clone() for x in o[:4]) for o in mb.outputs]
+    for y, t, y0, t0 in zip(Yw, Tw, Y0, T0):
+        y.copy_(y0)
+        t.copy_(t0)
+    torch.cuda.synchronize()
+    mb.capture()
+    for rep in range(3):
+        for y, t, y0, t0 in zip(Yw, Tw, Y0, T0):
+            y.copy_(y0)
+            t.copy_(t0)
+        torch.cuda.synchronize()
+        mb.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1000, device=dev).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        for o, e in zip(mb.outputs, eager):
+            for a, b in zip(o[:4], e):
+                assert torch.equal(a, b), f"replay {rep} differs"
+        del junk
+    for n in nets:
+        n.close()
+
+
+def test_autotune_then_burn(gpu, oracle):
+    cfg = synth.config(2, n_cells=4096)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = gpu.Network(spec)
+    res = gpu.autotune(net, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL)
+    timed = [r for r in res if r[3] is not None]
+    print(res, flush=True)
+    assert timed, res
+    best = min(timed, key=lambda r: r[3])
+    assert net.get_launch() == best[:3]
+    sub = cells.subset(np.arange(300))
+    g = _host(gpu.burn(net, sub.Y, sub.rho, sub.T, cfg.t_end, RTOL, ATOL))
+    _check(g, oracle, spec, sub, cfg.t_end)
+    net.set_launch(0, 0, 0)
+    net.close()

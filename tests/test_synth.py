@@ -101,3 +101,15 @@ def test_network_json_roundtrip_and_validation():
         for _ in range(bad.n_species):
             bad.validate()
             bad.products[0, 0] = (bad.products[0, 0] + 1) % bad.n_species
+
+
+@pytest.mark.parametrize("i", [2, 3, 4, 5])
+def test_networks_react_from_seed_composition(i):
+    """Every workload network has at least three reactions whose reactants
+    are all seed species, so a burn from the seed composition is not inert."""
+    cfg = synth.config(i, n_cells=4)
+    for net in cfg.networks:
+        seeds = set(synth.seed_species(net).tolist())
+        k = sum(all(s in seeds for s in net.reactants[r] if s >= 0)
+                for r in range(net.n_reactions))
+        assert k >= 3, (net.name, k)
