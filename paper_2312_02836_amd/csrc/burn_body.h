@@ -220,9 +220,9 @@ struct Unroll<0> {
 
 
 // ---------------------------------------------------------------------------
-// LDS layout.  Per workgroup, the network tables (ints first, so that the
-// 16-byte loads of a reaction's output list are aligned):
-//   rout[8R] rsp[4R] (ints) | rtab[8R] emult[R] q[R] qcv[R] (doubles)
+// LDS layout.  Per workgroup, the network tables (every array starts on a
+// 16-byte boundary, so a reaction's output list is one aligned 16-byte pair):
+//   rtab[8R] (doubles) | rout[8R] rsp[4R] (ints) | emult[R] q[R] qcv[R] (doubles)
 // then one area per wave:
 //   D[CPW][DS] ybuf[CPW][YS] facc[CPW][YS] fslot[FC][FB] fsc[FC][4]
 // with FB = NP + n*MS + 2*NP + 1 doubles per factorization slot: y_J, the
@@ -235,11 +235,15 @@ struct Unroll<0> {
 
 __host__ __device__ inline size_t tab_doubles_of(int R) { return 17 * (size_t)R; }
 
-__host__ __device__ inline int mat_stride(int n) { return n | 1; }
-
 template <int L, int S>
 struct Shape {
   static constexpr int NP = L * S;
+  // Small systems keep all NP rows with the compile-time stride NP + 1 (the
+  // padded rows are identity rows); large ones store only the n real rows
+  // with the odd stride n | 1, which keeps a 51-component matrix in 21 KB.
+  static constexpr bool COMPACT = NP >= 32;
+  __host__ __device__ static int ms(int n) { return COMPACT ? (n | 1) : NP + 1; }
+  __host__ __device__ static int rows(int n) { return COMPACT ? n : NP; }
   static constexpr int CPW = 64 / L;
   static constexpr int FL = NP;       // factor lanes per cell (one row each)
   static constexpr int FC = 64 / NP;  // cells per factorization pass
@@ -247,7 +251,7 @@ struct Shape {
   static constexpr int DS = DROWS * NP + 4;  // history stride per cell
   static constexpr int YS = NP + 4;          // exchange-vector stride per cell
   __host__ __device__ static size_t fb(int n) {
-    return (size_t)NP + (size_t)n * mat_stride(n) + 2 * (size_t)NP + 1;
+    return (size_t)NP + (size_t)rows(n) * ms(n) + 2 * (size_t)NP + 1;
   }
   __host__ __device__ static size_t wave_doubles(int n) {
     return (size_t)CPW * DS + 2 * (size_t)CPW * YS + FC * fb(n) + 4 * FC;
@@ -261,10 +265,10 @@ struct Tabs {
 
 __device__ __forceinline__ Tabs tabs_at(double *smem, int R) {
   Tabs t;
-  t.rout = reinterpret_cast<const int *>(smem);
+  t.rtab = smem;
+  t.rout = reinterpret_cast<const int *>(smem + 8 * (size_t)R);
   t.rsp = t.rout + 8 * R;
-  t.rtab = reinterpret_cast<const double *>(t.rsp + 4 * R);
-  t.emult = t.rtab + 8 * (size_t)R;
+  t.emult = reinterpret_cast<const double *>(t.rsp + 4 * R);
   t.q = t.emult + R;
   t.qcv = t.q + R;
   return t;
@@ -275,10 +279,10 @@ __device__ __forceinline__ Tabs tabs_at(double *smem, int R) {
 __device__ __forceinline__ void load_tables(const NetTables &nt, const double *log_mult,
                                             double *smem) {
   const int R = nt.R;
-  int *rout = reinterpret_cast<int *>(smem);
+  double *rtab = smem;
+  int *rout = reinterpret_cast<int *>(smem + 8 * (size_t)R);
   int *rsp = rout + 8 * R;
-  double *rtab = reinterpret_cast<double *>(rsp + 4 * R);
-  double *emult = rtab + 8 * (size_t)R;
+  double *emult = reinterpret_cast<double *>(rsp + 4 * R);
   double *q = emult + R;
   double *qcv = q + R;
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -308,7 +312,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 
   const NetTables &nt = a.net;
   const int N = nt.N, R = nt.R, n = nt.n;
-  const int MS = mat_stride(n);
+  const int MS = SH::ms(n);
+  const int MROWS = SH::rows(n);
   const size_t FB = SH::fb(n);
 
   const int lane = threadIdx.x & 63;
@@ -656,23 +661,26 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         }
       }
       wave_lds_sync();
-      // (b) factor layout: slot fj = lane / FL, row fi = lane % FL; the rows
-      // fi >= n of a padded system take no part
+      // (b) factor layout: slot fj = lane / FL, row fi = lane % FL; in the
+      // compact layout the rows fi >= n of a padded system take no part
       const int fj = lane / FL, fi = lane % FL;
       int fsel = -1;
 #pragma unroll
       for (int j = 0; j < FC; ++j)
         if (j == fj) fsel = sel[j];
       double *fy = fbase + (size_t)fj * FB;
-      double *fM = fy + NP;  // Newton matrix [n][MS], row-major
+      double *fM = fy + NP;  // Newton matrix [MROWS][MS], row-major
       const double fcc = fsel >= 0 ? fsc[4 * fj + 0] : 0.0;
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
-      const bool frow = fi < n;
+      const bool frow = fi < MROWS;
       if (frow) {
         double *mr = fM + fi * MS;
+        if constexpr (SH::COMPACT) {
+          for (int j = 0; j < MROWS; ++j) mr[j] = (fi == j) ? 1.0 : 0.0;
+        } else {
 #pragma unroll
-        for (int j = 0; j < NP; ++j)
-          if (j < n) mr[j] = (fi == j) ? 1.0 : 0.0;
+          for (int j = 0; j < NP; ++j) mr[j] = (fi == j) ? 1.0 : 0.0;
+        }
       }
       wave_lds_sync();
       // Rates at y_J for the reactions r = fi, fi+FL, ...; every Jacobian term
@@ -775,7 +783,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         wave_lds_sync();
       }
       // (d) the factors stay in LDS; publish position -> row and 1/U_pp
-      double *aux = fM + (size_t)n * MS;
+      double *aux = fM + (size_t)MROWS * MS;
       if (fsel >= 0) {
         if (frow) {
           aux[pos] = fdinv;
@@ -789,7 +797,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       wave_lds_sync();
       if (myslot >= 0) {
         const double *src = fbase + (size_t)myslot * FB + NP;
-        const double *saux = src + (size_t)n * MS;
+        const double *saux = src + (size_t)MROWS * MS;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           const int p = comp(s);
