@@ -1,15 +1,26 @@
-"""Benchmark: plain per-cell burn of the 13-species / 30-reaction synthetic
-network, 65,536 cells, dt = 1e-2, rtol 1e-6, atol 1e-10, FP64, one MI355X.
+"""Benchmark of the per-cell reaction burn on one MI355X (FP64, rtol 1e-6).
+
+Workloads (--workload):
+  synth13  (default) burn of the synthetic 13-species / 30-reaction
+           network, 65,536 cells, dt = 1e-2, in one persistent launch (the
+           fastest schedule for it), with the plain kernel (static map of
+           cells to lane groups, same shape) timed beside it;
+  mixed4   four networks (13/30, 21/60, 35/100, 50/150), 65,536 cells each,
+           in ONE persistent launch with a device work queue; the plain
+           kernel (one launch per network, same shapes) is timed beside it;
+  synth50  the 50-species / 150-reaction network, 1,048,576 cells, one
+           persistent launch, with the plain launch timed beside it.
 
 A step is one burn of the whole batch from the same initial state (the state
-is restored from a resident copy with a device-to-device copy inside the
-timed region).  Prints one JSON line.
+is restored from a resident copy with device-to-device copies inside the
+timed region, outside the kernel events).  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -18,10 +29,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 flop/clk x 2.4 GHz
-KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_kernels.hip",
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_body.h",
+                  "paper_2312_02836_amd/csrc/burn_multi.hip",
                   "paper_2312_02836_amd/csrc/burn_internal.h"]
-TRAFFIC_FILE = "profiles/burn_plain_kernel__synth13_30__65536cells__hbm_traffic.txt"
+TRAFFIC_FILE = "profiles/burn_multi_kernel__synth13_30__65536cells__hbm_traffic.txt"
+
+WORKLOADS = {
+    "synth13": dict(config=2, cells=65536, mode="persistent",
+                    text="burn of one synthetic 13-species/30-reaction network, {cells} cells, "
+                         "dt=1e-2, rtol 1e-6, atol 1e-10"),
+    "mixed4": dict(config=4, cells=65536, mode="persistent",
+                   text="mixed persistent burn, synthetic 13/30 + 21/60 + 35/100 + 50/150 "
+                        "species/reaction networks, {cells} cells each in one launch, dt=1e-2, "
+                        "rtol 1e-6, atol 1e-10"),
+    "synth50": dict(config=3, cells=1048576, mode="persistent",
+                    text="persistent burn, synthetic 50-species/150-reaction network, {cells} "
+                         "cells, T log-uniform [0.8, 6], dt=1e-2, rtol 1e-6, atol 1e-10"),
+}
 
 
 def kernel_sources_sha256() -> str:
@@ -44,7 +69,7 @@ def measured_traffic():
         for line in f:
             if "=" in line and not line.lstrip().startswith("#"):
                 k, v = line.split("=", 1)
-                kv[k.strip()] = v.strip()
+                kv[k.strip()] = v.split("#")[0].strip()
     if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     return float(kv["traffic_bytes_per_launch"])
@@ -55,9 +80,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cells", type=int, default=65536)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="synth13")
+    ap.add_argument("--cells", type=int, default=0, help="cells per network (0 = workload's)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block-waves", type=int, default=0)
+    ap.add_argument("--mode", choices=["plain", "persistent"], default=None,
+                    help="override the workload's launch mode")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="persistent workloads: skip timing the plain launches beside them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -72,34 +102,62 @@ def main() -> int:
     import numpy as np
     import torch
 
+    from paper_2312_02836_amd import _lib
     from paper_2312_02836_amd import burn as B
     from paper_2312_02836_amd import flops, synth
 
+    wl = dict(WORKLOADS[args.workload])
+    if args.mode:
+        wl["mode"] = args.mode
+    n_cells = args.cells or wl["cells"]
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    cfg = synth.config(2, n_cells=args.cells)
-    spec, cells = cfg.networks[0], cfg.cells[0]
-    net = B.Network(spec)
-    Y0 = torch.as_tensor(cells.Y, device=dev).contiguous()
-    T0 = torch.as_tensor(cells.T, device=dev).contiguous()
-    rho = torch.as_tensor(cells.rho, device=dev).contiguous()
-    Yw, Tw = Y0.clone(), T0.clone()
-    st = torch.empty(args.cells, dtype=torch.int32, device=dev)
-    cnt = torch.empty((8, args.cells), dtype=torch.int32, device=dev)
-
-    from paper_2312_02836_amd import _lib
-    import ctypes as C
-    opts = _lib.BurnOpts(0, args.lanes, args.block_waves, 0)
-    stream = torch.cuda.current_stream(dev)
+    cfg = synth.config(wl["config"], n_cells=n_cells)
     L = _lib.lib()
+    stream = torch.cuda.current_stream(dev)
 
-    def launch():
-        rc = L.burn_batch_ex(net.handle, args.cells, C.c_void_p(Yw.data_ptr()),
-                             C.c_void_p(rho.data_ptr()), C.c_void_p(Tw.data_ptr()), cfg.t_end,
-                             cfg.rtol, cfg.atol, None, C.c_void_p(st.data_ptr()),
-                             C.c_void_p(cnt.data_ptr()), C.byref(opts),
+    # resident inputs and working copies, per network
+    batches = []
+    for spec, cells in zip(cfg.networks, cfg.cells):
+        net = B.Network(spec)
+        if args.lanes:
+            net.set_launch(*_shape_for(spec.n, args.lanes), args.block_waves)
+        b = dict(spec=spec, cells=cells, net=net,
+                 Y0=torch.as_tensor(cells.Y, device=dev).contiguous(),
+                 T0=torch.as_tensor(cells.T, device=dev).contiguous(),
+                 rho=torch.as_tensor(cells.rho, device=dev).contiguous())
+        b["Yw"], b["Tw"] = b["Y0"].clone(), b["T0"].clone()
+        b["st"] = torch.empty(n_cells, dtype=torch.int32, device=dev)
+        b["cnt"] = torch.empty((8, n_cells), dtype=torch.int32, device=dev)
+        batches.append(b)
+    opts = _lib.BurnOpts(0, 0, args.block_waves, 0)
+
+    def restore():
+        for b in batches:
+            b["Yw"].copy_(b["Y0"])
+            b["Tw"].copy_(b["T0"])
+
+    def launch_plain(b):
+        rc = L.burn_batch_ex(b["net"].handle, n_cells, C.c_void_p(b["Yw"].data_ptr()),
+                             C.c_void_p(b["rho"].data_ptr()), C.c_void_p(b["Tw"].data_ptr()),
+                             cfg.t_end, cfg.rtol, cfg.atol, None, C.c_void_p(b["st"].data_ptr()),
+                             C.c_void_p(b["cnt"].data_ptr()), C.byref(opts),
                              C.c_void_p(stream.cuda_stream))
         _lib.check(rc, "burn_batch_ex")
+
+    multi = None
+    if wl["mode"] == "persistent":
+        multi = B.MultiBurn([(b["net"], b["Yw"], b["rho"], b["Tw"]) for b in batches], cfg.t_end,
+                            cfg.rtol, cfg.atol, block_waves=args.block_waves)
+        for b, o in zip(batches, multi.outputs):  # MultiBurn owns its status/counter tensors
+            b["st_m"], b["cnt_m"] = o[2], o[3]
+
+    def step_persistent():
+        multi.run()
+
+    def step_plain():
+        for b in batches:
+            launch_plain(b)
 
     if args.copy_probe_mib > 0:
         nb = args.copy_probe_mib << 20
@@ -112,59 +170,66 @@ def main() -> int:
               flush=True)
         del src, dst
 
-    for _ in range(args.warmup):
-        Yw.copy_(Y0)
-        Tw.copy_(T0)
-        launch()
-    torch.cuda.synchronize()
-    print(f"bench: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    def timed(step, label):
+        for _ in range(args.warmup):
+            restore()
+            step()
+        torch.cuda.synchronize()
+        print(f"bench: {label}: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+        ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            restore()
+            ev0[i].record(stream)
+            step()
+            ev1[i].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
+        print(f"bench: {label}: {args.steps} steps, {1000 * wall / args.steps:.3f} ms/step, "
+              f"kernel {np.mean(kms):.3f} ms (min {min(kms):.3f})", file=sys.stderr, flush=True)
+        return 1000.0 * wall / args.steps, float(np.mean(kms))
 
-    k_start = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    k_end = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        Yw.copy_(Y0)
-        Tw.copy_(T0)
-        k_start[i].record(stream)
-        launch()
-        k_end[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = [a.elapsed_time(b) for a, b in zip(k_start, k_end)]
-    ms_per_step = 1000.0 * wall / args.steps
+    plain_ms = plain_kernel_ms = None
+    if wl["mode"] == "plain":
+        ms_per_step, kernel_ms = timed(step_plain, "plain")
+        outs = [(b["st"], b["cnt"]) for b in batches]
+        kernel_name = "burn_plain_kernel"
+    else:
+        if not args.no_plain:
+            plain_ms, plain_kernel_ms = timed(step_plain, "plain (one launch per network)")
+        ms_per_step, kernel_ms = timed(step_persistent, "persistent (one launch)")
+        outs = [(b["st_m"], b["cnt_m"]) for b in batches]
+        kernel_name = "burn_multi_kernel"
 
-    status = st.cpu().numpy()
-    counters = cnt.cpu().numpy()
-    n_ok = int((status == 0).sum())
+    n_ok, f_launch = 0, 0.0
+    for b, (st, cnt) in zip(batches, outs):
+        s = st.cpu().numpy()
+        n_ok += int((s == 0).sum())
+        f_launch += flops.total_flops(b["spec"], cnt.cpu().numpy())
+    n_total = n_cells * len(batches)
     value = n_ok / (ms_per_step / 1000.0)
-    kernel_avg_ms = float(np.mean(kernel_ms))
-    f_launch = flops.total_flops(spec, counters)
-    achieved = f_launch / (kernel_avg_ms / 1000.0) / 1e12
-    print(f"bench: {args.steps} steps, {ms_per_step:.3f} ms/step, kernel {kernel_avg_ms:.3f} ms "
-          f"(min {min(kernel_ms):.3f}), ok {n_ok}/{args.cells}, "
-          f"alg flops/launch {f_launch:.4e}", file=sys.stderr, flush=True)
+    achieved = f_launch / (kernel_ms / 1000.0) / 1e12
+    print(f"bench: ok {n_ok}/{n_total}, alg flops/launch {f_launch:.4e}", file=sys.stderr,
+          flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
-        from oracle import oracle
-        onet = oracle.OracleNet(spec)
-        threads = oracle.max_threads()
-        n_s = 512
-        rng = np.random.default_rng(1234)
-        while True:
-            idx = np.sort(rng.choice(cells.n_cells, min(n_s, cells.n_cells), replace=False))
-            sub = cells.subset(idx)
-            tc = time.perf_counter()
-            oracle.burn(onet, sub, cfg.t_end, cfg.rtol, cfg.atol)
-            el = time.perf_counter() - tc
-            if el >= args.cpu_seconds or n_s >= cells.n_cells:
-                break
-            n_s = min(cells.n_cells, int(n_s * max(2.0, 1.2 * args.cpu_seconds / max(el, 1e-3))))
-        cpu = {"value": len(idx) / el, "unit": "cell-burns/s", "cores": threads, "kind": "oracle",
-               "sample": f"{len(idx)} seeded random cells of the same 65,536-cell workload, "
-                         f"{el:.1f} s on {threads} OpenMP threads"}
+        cpu = cpu_baseline(batches, cfg, args.cpu_seconds)
 
+    traffic = None
+    if (args.workload == "synth13" and wl["mode"] == "persistent"
+            and (n_cells, args.lanes, args.block_waves) == (65536, 0, 0)):
+        traffic = measured_traffic()
+    config = {"workload": wl["text"].format(cells=n_cells), "cells_per_network": n_cells,
+              "networks": [f"{b['spec'].n_species}/{b['spec'].n_reactions}" for b in batches],
+              "t_end": cfg.t_end, "kernel": kernel_name,
+              "launch": [list(b["net"].get_launch()) for b in batches]}
+    if plain_ms is not None:
+        config.update({"plain_ms_per_step": plain_ms, "plain_kernel_ms": plain_kernel_ms,
+                       "vs_plain": plain_kernel_ms / kernel_ms})
     out = {
         "metric": "cell-burns/s (FP64, rtol 1e-6)",
         "value": value,
@@ -178,21 +243,51 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "plain burn, synthetic 13-species/30-reaction network, "
-                               f"{args.cells} cells, dt=1e-2, rtol 1e-6, atol 1e-10",
-                   "cells": args.cells, "species": spec.n_species, "reactions": spec.n_reactions,
-                   "t_end": cfg.t_end, "kernel": "burn_plain_kernel",
-                   "lanes_per_cell": args.lanes or "auto"},
+        "config": config,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": (measured_traffic() if (args.cells, args.lanes, args.block_waves) == (65536, 0, 0)
-                                 else None),
-                     "kernel_ms": kernel_avg_ms, "alg_flops_per_launch": f_launch},
+                     "traffic": traffic, "kernel_ms": kernel_ms,
+                     "alg_flops_per_launch": f_launch},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    net.close()
+    for b in batches:
+        b["net"].close()
     return 0
+
+
+def _shape_for(n: int, lanes: int):
+    """Smallest padded shape with the given lanes per cell."""
+    for L_, S_ in ((4, 1), (4, 2), (4, 4), (8, 4), (16, 2), (32, 1), (16, 4), (32, 2), (64, 1)):
+        if L_ == lanes and L_ * S_ >= n:
+            return L_, S_
+    raise SystemExit(f"no shape with {lanes} lanes per cell for a system of size {n}")
+
+
+def cpu_baseline(batches, cfg, seconds: float):
+    """The oracle on the host cores, on a seeded sample of the same cells
+    (the same fraction of every network), scaled to cell-burns/s."""
+    import numpy as np
+    from oracle import oracle
+    threads = oracle.max_threads()
+    onets = [oracle.OracleNet(b["spec"]) for b in batches]
+    C_ = batches[0]["cells"].n_cells
+    frac = min(1.0, 512.0 / C_)
+    rng = np.random.default_rng(1234)
+    while True:
+        k = max(1, int(round(frac * C_)))
+        idx = np.sort(rng.choice(C_, k, replace=False))
+        tc = time.perf_counter()
+        for b, on in zip(batches, onets):
+            oracle.burn(on, b["cells"].subset(idx), cfg.t_end, cfg.rtol, cfg.atol)
+        el = time.perf_counter() - tc
+        if el >= seconds or frac >= 1.0:
+            break
+        frac = min(1.0, frac * max(2.0, 1.2 * seconds / max(el, 1e-3)))
+    n = k * len(batches)
+    return {"value": n / el, "unit": "cell-burns/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} seeded random cells of each of the {len(batches)} network(s) of the "
+                      f"same workload ({n} cells), {el:.1f} s on {threads} OpenMP threads"}
 
 
 if __name__ == "__main__":
