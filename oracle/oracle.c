@@ -290,22 +290,22 @@ static double rising_binom(double s, int j) {
  * those values again: D'_a = sum_{m=0..a} (-1)^m C(a, m) p(-m rho_h).
  * D is stored row-major with n columns. */
 void orc_rescale(int n, int k, double *D, double rho_h) {
-  double v[ORC_KMAX + 1][ORC_NMAX];
-  for (int m = 0; m <= k; m++) {
-    double s = -(double)m * rho_h;
-    for (int i = 0; i < n; i++) {
+  /* column by column: values of the interpolant at the new nodes, then
+   * their backward differences */
+  for (int i = 0; i < n; i++) {
+    double v[ORC_KMAX + 1];
+    for (int m = 0; m <= k; m++) {
+      double s = -(double)m * rho_h;
       double acc = 0.0;
       for (int j = 0; j <= k; j++) acc += rising_binom(s, j) * D[j * n + i];
-      v[m][i] = acc;
+      v[m] = acc;
     }
-  }
-  for (int a = 0; a <= k; a++) {
-    for (int i = 0; i < n; i++) {
+    for (int a = 0; a <= k; a++) {
       double acc = 0.0;
       double binom = 1.0; /* C(a, m) */
       for (int m = 0; m <= a; m++) {
         double sign = (m % 2) ? -1.0 : 1.0;
-        acc += sign * binom * v[m][i];
+        acc += sign * binom * v[m];
         binom = binom * (double)(a - m) / (double)(m + 1);
       }
       D[a * n + i] = acc;
@@ -329,11 +329,36 @@ static int all_finite(int n, const double *v) {
 #define NEWTON_MAXIT 4
 #define NEWTON_TOL 0.03
 
+/* The frozen control decisions of a burn (what a sensitivity run replays):
+ * the initial step size and, per accepted step, its BDF order, its step size
+ * and the product of the history rescale ratios applied since the previous
+ * accepted step (clamp onto t_end, rejections, Newton failures and the step
+ * change chosen after the previous step).  Every rescale between two accepted
+ * steps acts at the order of the later step. */
+typedef struct {
+  int cap;          /* capacity of the arrays */
+  int n_steps;      /* accepted steps recorded */
+  double h_init;    /* D_1 = h_init f(y0) */
+  double *h;        /* [cap] */
+  double *ratio;    /* [cap] */
+  int32_t *order;   /* [cap] */
+} orc_schedule;
+
+static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const double *log_mult,
+                          const orc_opts *o, int32_t *cnt, orc_schedule *sch);
+
 /* Integrate one cell from t = 0 to t_end.  y_io holds (Y, T) on entry and
  * the last accepted state on exit.  cnt receives the eight counters.  Returns
  * the status code. */
 int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *log_mult,
                   const orc_opts *o, int32_t *cnt) {
+  return burn_cell_impl(net, rho, y_io, log_mult, o, cnt, NULL);
+}
+
+/* The integrator; when sch is not NULL the schedule is recorded (up to
+ * sch->cap steps, which must be >= o->max_steps). */
+static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const double *log_mult,
+                          const orc_opts *o, int32_t *cnt, orc_schedule *sch) {
   const int N = net->n_species, n = N + 1;
   const double rtol = o->rtol, atol = o->atol, t_end = o->t_end;
   double D[(K_MAX + 3) * ORC_NMAX];
@@ -392,6 +417,7 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
     if (t_end < h) h = t_end;
 
     /* History: D_0 = y0, D_1 = h f0, the rest zero; order 1. */
+    if (sch) { sch->h_init = h; sch->n_steps = 0; }
     k = 1;
     memset(D, 0, sizeof(D));
     for (int i = 0; i < n; i++) { D[i] = y0[i]; D[n + i] = h * f0[i]; }
@@ -403,6 +429,7 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
 
   int status = ORC_OK;
   double err = 0.0;
+  double racc = 1.0; /* rescale ratios since the last accepted step */
   while (t < t_end) {
     if (cnt[C_STEPS] >= o->max_steps) { status = ORC_MAX_STEPS; break; }
     /* ---- one accepted step (with rejections and retries) ---- */
@@ -418,6 +445,7 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
       if (t_new > t_end) {
         t_new = t_end;
         orc_rescale(n, k, D, (t_end - t) / h);
+        racc *= (t_end - t) / h;
         h = t_end - t;
         n_eq = 0;
         lu_valid = 0;
@@ -484,6 +512,7 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
         /* Halve the step and retry. */
         h *= 0.5;
         orc_rescale(n, k, D, 0.5);
+        racc *= 0.5;
         n_eq = 0;
         lu_valid = 0;
         continue;
@@ -501,6 +530,7 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
         if (factor < MIN_FACTOR) factor = MIN_FACTOR;
         h *= factor;
         orc_rescale(n, k, D, factor);
+        racc *= factor;
         n_eq = 0;
         lu_valid = 0;
         cnt[C_REJ_ERR]++;
@@ -520,6 +550,13 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
       for (int i = 0; i < n; i++) D[j * n + i] += D[(j + 1) * n + i];
     jac_current = 0;
     n_eq++;
+    if (sch && sch->n_steps < sch->cap) {
+      sch->h[sch->n_steps] = h;
+      sch->ratio[sch->n_steps] = racc;
+      sch->order[sch->n_steps] = k;
+      sch->n_steps++;
+    }
+    racc = 1.0;
     cnt[C_STEPS]++;
     if (o->fixed_order) continue;
 
@@ -546,6 +583,7 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
       if (factor > MAX_FACTOR) factor = MAX_FACTOR;
       h *= factor;
       orc_rescale(n, k, D, factor);
+      racc *= factor;
       n_eq = 0;
       lu_valid = 0;
     }
@@ -553,6 +591,210 @@ int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *lo
   cnt[C_ORDER] = k;
   memcpy(y_io, D, sizeof(double) * n);
   return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sensitivities with respect to the log-rate multipliers                    */
+/* ------------------------------------------------------------------------ */
+
+/* The question the paper asks of its networks is how the burn responds to
+ * the individual rates (Sec. 1).  What is differentiated here is the burn
+ * replayed on its own frozen schedule (orders, step sizes, rescale ratios of
+ * the recorded run) with every corrector solved exactly, i.e. the discrete
+ * map y0 -> y_end that the recorded run approximates to its Newton tolerance.
+ * Its tangent-linear model gives S = d y_end / d p (forward sensitivities). */
+
+#define ADJ_NEWTON_MAXIT 8
+#define ADJ_NEWTON_TOL 1e-10
+
+/* df/dp at y: Fp[i*R + r] = W_ir R_r, W = nu for a species row and q_r / c_v
+ * for the temperature row (d R_r / d p_r = R_r). */
+static void rhs_dlogmult(const orc_net *net, double rho, const double *y, const double *log_mult,
+                         double *Fp) {
+  int N = net->n_species, Rn = net->n_reactions;
+  double R[ORC_RMAX], lam[ORC_RMAX];
+  reaction_rates(net, rho, y, log_mult, R, lam, NULL);
+  for (int i = 0; i < N; i++)
+    for (int r = 0; r < Rn; r++) Fp[i * Rn + r] = (double)nu(net, i, r) * R[r];
+  for (int r = 0; r < Rn; r++) Fp[N * Rn + r] = net->q[r] * R[r] / net->c_v;
+}
+
+/* Newton matrix I - c J(y) and its factors. */
+static int newton_matrix(const orc_net *net, double rho, const double *y, const double *log_mult,
+                         double c, double *J, double *LU, int *piv) {
+  int n = net->n_species + 1;
+  orc_jac(net, rho, y, log_mult, J);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) LU[i * n + j] = (i == j ? 1.0 : 0.0) - c * J[i * n + j];
+  return orc_lu_factor(n, LU, piv);
+}
+
+/* Replay schedule sch from y0 (y_io on entry) with exact correctors: full
+ * Newton (Jacobian and factors at every iterate) from the predictor until the
+ * weighted norm of the increment is <= ADJ_NEWTON_TOL, at most
+ * ADJ_NEWTON_MAXIT iterations.  y_io receives y_end.  With S != NULL the
+ * tangent-linear model is carried along and S (n x R, row-major) receives
+ * d y_end / d p.  *n_unconv counts correctors that stopped at the iteration
+ * limit.  Returns ORC_OK or ORC_NONFINITE (non-finite or singular corrector). */
+int orc_replay_cell(const orc_net *net, double rho, double *y_io, const double *log_mult,
+                    const orc_schedule *sch, double rtol, double atol, double *S, int *n_unconv) {
+  const int N = net->n_species, n = N + 1, Rn = net->n_reactions;
+  const int nc = n * Rn;
+  double D[(K_MAX + 3) * ORC_NMAX];
+  double J[ORC_NMAX * ORC_NMAX], LU[ORC_NMAX * ORC_NMAX];
+  int piv[ORC_NMAX];
+  double f0[ORC_NMAX], ypred[ORC_NMAX], psi[ORC_NMAX], s[ORC_NMAX], d[ORC_NMAX], y[ORC_NMAX];
+  double F[ORC_NMAX], dy[ORC_NMAX];
+  double *SD = NULL, *Fp = NULL, *Sy0 = NULL, *Spsi = NULL, *Sd = NULL;
+  int status = ORC_OK;
+  *n_unconv = 0;
+  if (S) {
+    SD = (double *)calloc((size_t)(K_MAX + 3) * nc, sizeof(double));
+    Fp = (double *)malloc(sizeof(double) * nc);
+    Sy0 = (double *)malloc(sizeof(double) * nc);
+    Spsi = (double *)malloc(sizeof(double) * nc);
+    Sd = (double *)malloc(sizeof(double) * nc);
+  }
+  memset(D, 0, sizeof(D));
+  orc_rhs(net, rho, y_io, log_mult, f0);
+  for (int i = 0; i < n; i++) { D[i] = y_io[i]; D[n + i] = sch->h_init * f0[i]; }
+  if (S) {
+    rhs_dlogmult(net, rho, y_io, log_mult, Fp);
+    for (int q = 0; q < nc; q++) SD[nc + q] = sch->h_init * Fp[q];
+  }
+  for (int m = 0; m < sch->n_steps && status == ORC_OK; m++) {
+    const int k = sch->order[m];
+    const double h = sch->h[m], ratio = sch->ratio[m];
+    if (ratio != 1.0) {
+      orc_rescale(n, k, D, ratio);
+      if (S) orc_rescale(nc, k, SD, ratio);
+    }
+    double gk = bdf_gamma(k);
+    for (int i = 0; i < n; i++) {
+      double a = 0.0;
+      for (int j = 0; j <= k; j++) a += D[j * n + i];
+      ypred[i] = a;
+      double b = 0.0;
+      for (int j = 1; j <= k; j++) b += bdf_gamma(j) * D[j * n + i];
+      psi[i] = b / gk;
+      s[i] = atol + rtol * fabs(ypred[i]);
+      d[i] = 0.0;
+      y[i] = ypred[i];
+    }
+    double cc = h / gk;
+    int conv = 0;
+    for (int it = 0; it < ADJ_NEWTON_MAXIT; it++) {
+      orc_rhs(net, rho, y, log_mult, F);
+      if (newton_matrix(net, rho, y, log_mult, cc, J, LU, piv)) { status = ORC_NONFINITE; break; }
+      for (int i = 0; i < n; i++) dy[i] = cc * F[i] - psi[i] - d[i];
+      orc_lu_solve(n, LU, piv, dy);
+      double dn = wrms(n, dy, s);
+      if (!isfinite(dn)) { status = ORC_NONFINITE; break; }
+      for (int i = 0; i < n; i++) { y[i] += dy[i]; d[i] += dy[i]; }
+      if (dn <= ADJ_NEWTON_TOL) { conv = 1; break; }
+    }
+    if (status != ORC_OK) break;
+    if (!conv) (*n_unconv)++;
+    if (S) {
+      /* d' = M^-1 (c J y0' - psi' + c f_p), all at the corrected state */
+      if (newton_matrix(net, rho, y, log_mult, cc, J, LU, piv)) { status = ORC_NONFINITE; break; }
+      rhs_dlogmult(net, rho, y, log_mult, Fp);
+      for (int q = 0; q < nc; q++) {
+        double a = 0.0;
+        for (int j = 0; j <= k; j++) a += SD[j * nc + q];
+        Sy0[q] = a;
+        double b = 0.0;
+        for (int j = 1; j <= k; j++) b += bdf_gamma(j) * SD[j * nc + q];
+        Spsi[q] = b / gk;
+      }
+      for (int r = 0; r < Rn; r++) {
+        double col[ORC_NMAX];
+        for (int i = 0; i < n; i++) {
+          double jy = 0.0;
+          for (int j = 0; j < n; j++) jy += J[i * n + j] * Sy0[j * Rn + r];
+          col[i] = cc * jy - Spsi[i * Rn + r] + cc * Fp[i * Rn + r];
+        }
+        orc_lu_solve(n, LU, piv, col);
+        for (int i = 0; i < n; i++) Sd[i * Rn + r] = col[i];
+      }
+    }
+    /* the history update of an accepted step, for D and its tangent */
+    for (int i = 0; i < n; i++) {
+      D[(k + 2) * n + i] = d[i] - D[(k + 1) * n + i];
+      D[(k + 1) * n + i] = d[i];
+    }
+    for (int j = k; j >= 0; j--)
+      for (int i = 0; i < n; i++) D[j * n + i] += D[(j + 1) * n + i];
+    if (S) {
+      for (int q = 0; q < nc; q++) {
+        SD[(k + 2) * nc + q] = Sd[q] - SD[(k + 1) * nc + q];
+        SD[(k + 1) * nc + q] = Sd[q];
+      }
+      for (int j = k; j >= 0; j--)
+        for (int q = 0; q < nc; q++) SD[j * nc + q] += SD[(j + 1) * nc + q];
+    }
+  }
+  if (status == ORC_OK) {
+    memcpy(y_io, D, sizeof(double) * n);
+    if (S) memcpy(S, SD, sizeof(double) * nc);
+  }
+  free(SD); free(Fp); free(Sy0); free(Spsi); free(Sd);
+  return status;
+}
+
+/* Per cell: burn with log_mult recording the schedule, then replay that
+ * schedule from the same initial state with log_mult_replay (NULL: the same
+ * multipliers), optionally with forward sensitivities.  Y, T receive the
+ * replayed end state (the recorded run's state for a cell whose burn
+ * failed); status the burn's status, or NONFINITE if the replay failed;
+ * counters the burn's counters; S [C][n][R] (or NULL) the sensitivities,
+ * zero for a failed cell; n_unconv [C] (or NULL) the correctors that hit the
+ * iteration limit. */
+int orc_sens_batch(const orc_net *net, int64_t n_cells, double *Y, const double *rho, double *T,
+                   const double *log_mult, const double *log_mult_replay, const orc_opts *o,
+                   int32_t *status, int32_t *counters, double *S, int32_t *n_unconv,
+                   int n_threads) {
+  int N = net->n_species, n = N + 1, Rn = net->n_reactions;
+  if (N < 1 || n > ORC_NMAX || Rn < 1 || Rn > ORC_RMAX || n_cells < 0 || o->fixed_order)
+    return -1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t c = 0; c < n_cells; c++) {
+    double y[ORC_NMAX], y0[ORC_NMAX];
+    int32_t cnt[C_COUNT];
+    orc_schedule sch;
+    sch.cap = o->max_steps;
+    sch.n_steps = 0;
+    sch.h_init = 0.0;
+    sch.h = (double *)malloc(sizeof(double) * sch.cap);
+    sch.ratio = (double *)malloc(sizeof(double) * sch.cap);
+    sch.order = (int32_t *)malloc(sizeof(int32_t) * sch.cap);
+    for (int i = 0; i < N; i++) y[i] = Y[(int64_t)i * n_cells + c];
+    y[N] = T[c];
+    memcpy(y0, y, sizeof(double) * n);
+    int st = burn_cell_impl(net, rho[c], y, log_mult, o, cnt, &sch);
+    double *Sc = S ? S + (size_t)c * n * Rn : NULL;
+    int unc = 0;
+    if (st == ORC_OK) {
+      int rs = orc_replay_cell(net, rho[c], y0, log_mult_replay ? log_mult_replay : log_mult,
+                               &sch, o->rtol, o->atol, Sc, &unc);
+      if (rs == ORC_OK) memcpy(y, y0, sizeof(double) * n);
+      else st = rs;
+    }
+    if (Sc && st != ORC_OK) memset(Sc, 0, sizeof(double) * n * Rn);
+    for (int i = 0; i < N; i++) Y[(int64_t)i * n_cells + c] = y[i];
+    T[c] = y[N];
+    if (status) status[c] = st;
+    if (counters)
+      for (int j = 0; j < C_COUNT; j++) counters[(int64_t)j * n_cells + c] = cnt[j];
+    if (n_unconv) n_unconv[c] = unc;
+    free(sch.h); free(sch.ratio); free(sch.order);
+  }
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */

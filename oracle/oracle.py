@@ -69,6 +69,10 @@ def lib():
         L.orc_burn_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, C.POINTER(_Opts),
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int]
         L.orc_burn_batch.restype = C.c_int
+        L.orc_sens_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, dp,
+                                     C.POINTER(_Opts), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32), C.c_int]
+        L.orc_sens_batch.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -210,3 +214,38 @@ def burn(net: OracleNet, cells, t_end: float, rtol: float = 1e-6, atol: float = 
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def sens(net: OracleNet, cells, t_end: float, rtol: float = 1e-6, atol: float = 1e-10,
+         log_mult=None, log_mult_replay=None, want_S: bool = True, max_steps: int = 100000,
+         n_threads: int = 0):
+    """Record each cell's schedule with log_mult, replay it with exact
+    correctors and log_mult_replay (default: log_mult), with forward
+    sensitivities.  Returns (Y_end[N,C], T_end[C], status[C], counters[8,C],
+    S[C,n,R] = d y_end / d p or None, n_unconv[C])."""
+    Y = np.array(cells.Y, dtype=np.float64, order="C", copy=True)
+    T = np.array(cells.T, dtype=np.float64, copy=True)
+    rho = np.ascontiguousarray(cells.rho, dtype=np.float64)
+    C_ = rho.shape[0]
+    st = np.zeros(C_, dtype=np.int32)
+    cnt = np.zeros((8, C_), dtype=np.int32)
+    unc = np.zeros(C_, dtype=np.int32)
+    S = np.zeros((C_, net.n, net.R)) if want_S else None
+    lm = _lm(net, log_mult)
+    lmr = _lm(net, log_mult_replay)
+    o = _opts(t_end, rtol, atol, max_steps)
+    i32 = C.POINTER(C.c_int32)
+    rc = lib().orc_sens_batch(C.byref(net.c), C_, _dp(Y), _dp(rho), _dp(T), _dp(lm), _dp(lmr),
+                              C.byref(o), st.ctypes.data_as(i32), cnt.ctypes.data_as(i32),
+                              _dp(S), unc.ctypes.data_as(i32), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the network size")
+    return Y, T, st, cnt, S, unc
+
+
+def vjp(net: OracleNet, S, gY, gE) -> np.ndarray:
+    """Per-cell gradient [R, C] of sum_i gY_i Y_i + gE E (E = c_v (T - T0))
+    from forward sensitivities S [C, n, R]."""
+    g = np.vstack([np.asarray(gY, dtype=np.float64),
+                   net.spec.c_v * np.asarray(gE, dtype=np.float64)[None, :]])  # [n, C]
+    return np.einsum("cnr,nc->rc", S, g)
