@@ -204,6 +204,74 @@ int bn_network_set_launch(bn_network *net, int32_t lanes_per_cell, int32_t slots
 int bn_network_get_launch(const bn_network *net, int32_t *lanes_per_cell,
                           int32_t *slots_per_lane, int32_t *block_waves);
 
+/* ---- Sensitivities: discrete adjoint in the log-rate multipliers ------- */
+
+/* The paper asks how a burn responds to the individual reaction rates
+ * (Sec. 1).  These calls differentiate, cell by cell, the end state
+ * (Y, T)(dt) and the released energy E = c_v (T(dt) - T0) with respect to the
+ * network's log-rate multipliers p_r (lambda_r -> e^{p_r} lambda_r).  The
+ * differentiated map is the burn replayed on its own frozen schedule: a
+ * recording run (the same integrator as burn_batch) fixes every accepted
+ * step's order, step size and history rescale ratio, and the replay solves
+ * every corrector exactly (full Newton to a weighted increment <= 1e-10).
+ * The replay's end state is what the forward call returns; it agrees with
+ * burn_batch's to the integrator's Newton tolerance.  The reverse sweep keeps
+ * a checkpoint of the history every 16 accepted steps and recomputes each
+ * segment.
+ *
+ * Workspace: caller-provided DEVICE memory of
+ * burn_batch_adjoint_workspace_bytes(net, n_cells, max_steps) bytes, 8-byte
+ * aligned, holding the schedules and checkpoints; the forward call fills it,
+ * the backward call reads it (same net, cells, dt, tolerances, log_mult and
+ * max_steps), and it must not be shared by calls in flight.
+ * max_steps (1 .. 1,000,000) bounds the accepted steps of a cell; a cell that
+ * needs more ends with BN_CELL_MAX_STEPS and a zero gradient.
+ * Networks with more than BN_ADJOINT_MAX_REACTIONS reactions are not
+ * supported (BN_EUNSUPPORTED). */
+#define BN_ADJOINT_MAX_REACTIONS 256
+
+size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells,
+                                          int32_t max_steps);
+
+/* Forward: recording run plus replay.
+ *   state0, T0  DEVICE [N][n_cells], [n_cells]  initial state (read only)
+ *   rho         DEVICE [n_cells]
+ *   log_mult    DEVICE [R] or NULL
+ *   state_out   DEVICE [N][n_cells]  replayed end abundances
+ *   T_out       DEVICE [n_cells]     replayed end temperature
+ *   E_out       DEVICE [n_cells]     c_v (T_out - T0)
+ *   status      DEVICE [n_cells]     BN_CELL_* (required: the backward call
+ *                                    reads it)
+ *   counters    DEVICE [BN_N_COUNTERS][n_cells] or NULL (recording run)
+ * A cell that fails keeps the recording run's last accepted state. */
+int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const double *state0,
+                               const double *rho, const double *T0, double dt, double rtol,
+                               double atol, const double *log_mult, int32_t max_steps,
+                               double *state_out, double *T_out, double *E_out,
+                               int32_t *status, int32_t *counters, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/* Backward: per-cell vector-Jacobian product.
+ *   gY    DEVICE [N][n_cells]   cotangent of the end abundances
+ *   gE    DEVICE [n_cells]      cotangent of E
+ *   grad  DEVICE [R][n_cells]   out: sum_i gY_i dY_i/dp_r + gE dE/dp_r per
+ *                               cell (zero for a cell whose status is not OK)
+ *   status DEVICE [n_cells]     as written by the forward call */
+int burn_batch_adjoint_backward(const bn_network *net, int64_t n_cells, const double *state0,
+                                const double *rho, const double *T0, double dt, double rtol,
+                                double atol, const double *log_mult, int32_t max_steps,
+                                const double *gY, const double *gE, double *grad,
+                                const int32_t *status, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+/* Forward and backward in one call. */
+int burn_batch_adjoint(const bn_network *net, int64_t n_cells, const double *state0,
+                       const double *rho, const double *T0, double dt, double rtol, double atol,
+                       const double *log_mult, int32_t max_steps, const double *gY,
+                       const double *gE, double *state_out, double *T_out, double *E_out,
+                       double *grad, int32_t *status, int32_t *counters, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
 /* Thread-local description of the last failed call on this thread ("" if
  * none); valid until the next call from the same thread. */
 const char *bn_last_error(void);

@@ -22,7 +22,9 @@ COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "
 EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "bn_network_n_reactions", "burn_batch", "burn_batch_ex",
            "burn_batch_multi_workspace_bytes", "burn_batch_multi", "bn_network_autotune",
-           "bn_network_set_launch", "bn_network_get_launch", "bn_last_error", "bn_version"]
+           "bn_network_set_launch", "bn_network_get_launch",
+           "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
+           "burn_batch_adjoint_backward", "burn_batch_adjoint", "bn_last_error", "bn_version"]
 MAX_ITEMS = 8
 
 
@@ -90,6 +92,20 @@ def lib() -> C.CDLL:
     L.bn_network_get_launch.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32)]
     L.bn_network_get_launch.restype = C.c_int
+    L.burn_batch_adjoint_workspace_bytes.argtypes = [vp, C.c_int64, C.c_int32]
+    L.burn_batch_adjoint_workspace_bytes.restype = C.c_size_t
+    L.burn_batch_adjoint_forward.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
+                                             C.c_double, dp, C.c_int32, dp, dp, dp, ip, ip, vp,
+                                             C.c_size_t, vp]
+    L.burn_batch_adjoint_forward.restype = C.c_int
+    L.burn_batch_adjoint_backward.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
+                                              C.c_double, dp, C.c_int32, dp, dp, dp, ip, vp,
+                                              C.c_size_t, vp]
+    L.burn_batch_adjoint_backward.restype = C.c_int
+    L.burn_batch_adjoint.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
+                                     C.c_double, dp, C.c_int32, dp, dp, dp, dp, dp, dp, ip, ip,
+                                     vp, C.c_size_t, vp]
+    L.burn_batch_adjoint.restype = C.c_int
     L.bn_last_error.restype = C.c_char_p
     L.bn_version.restype = C.c_char_p
     _lib = L

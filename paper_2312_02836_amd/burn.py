@@ -225,3 +225,84 @@ def autotune(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float
     _lib.check(rc, "bn_network_autotune")
     return [(r.lanes_per_cell, r.slots_per_lane, r.block_waves, r.ms if r.status == 0 else None)
             for r in res[:nres.value]]
+
+
+class AdjointRun:
+    """A sensitivity run over a batch of cells: ``forward()`` records each
+    cell's schedule and replays it (end state, released energy E), then
+    ``backward(gY, gE)`` returns the per-cell gradients [R, C] of
+    sum_i gY_i Y_i + gE E with respect to the log-rate multipliers.  The
+    workspace (schedules and checkpoints) is allocated here, from torch."""
+
+    def __init__(self, net: Network, Y0, rho, T0, dt: float, rtol: float = 1e-6,
+                 atol: float = 1e-10, log_mult=None, *, max_steps: int = 2048,
+                 device: Optional[torch.device] = None):
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.net, self.dt, self.rtol, self.atol = net, float(dt), float(rtol), float(atol)
+        self.max_steps = int(max_steps)
+        self.Y0 = _dev_f64(Y0, device)
+        self.T0 = _dev_f64(T0, device)
+        self.rho = _dev_f64(rho, device)
+        self.C = self.rho.shape[0]
+        if self.Y0.shape != (net.n_species, self.C) or self.T0.shape != (self.C,):
+            raise ValueError("shapes of Y0, rho, T0 do not match")
+        self.lm = None if log_mult is None else _dev_f64(log_mult, device)
+        nb = _lib.lib().burn_batch_adjoint_workspace_bytes(net.handle, self.C, self.max_steps)
+        self.ws = torch.empty(max(nb, 8), dtype=torch.uint8, device=device)
+        self.Y = torch.empty_like(self.Y0)
+        self.T = torch.empty_like(self.T0)
+        self.E = torch.empty_like(self.T0)
+        self.status = torch.empty(self.C, dtype=torch.int32, device=device)
+        self.counters = torch.empty((8, self.C), dtype=torch.int32, device=device)
+        self.device = device
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self):
+        rc = _lib.lib().burn_batch_adjoint_forward(
+            self.net.handle, self.C, _ptr(self.Y0), _ptr(self.rho), _ptr(self.T0), self.dt,
+            self.rtol, self.atol, _ptr(self.lm), self.max_steps, _ptr(self.Y), _ptr(self.T),
+            _ptr(self.E), _ptr(self.status), _ptr(self.counters), _ptr(self.ws), self.ws.numel(),
+            self._stream())
+        _lib.check(rc, "burn_batch_adjoint_forward")
+        return self.Y, self.T, self.E, self.status
+
+    def backward(self, gY, gE) -> torch.Tensor:
+        gY = _dev_f64(gY, self.device)
+        gE = _dev_f64(gE, self.device)
+        grad = torch.empty((self.net.n_reactions, self.C), dtype=torch.float64, device=self.device)
+        rc = _lib.lib().burn_batch_adjoint_backward(
+            self.net.handle, self.C, _ptr(self.Y0), _ptr(self.rho), _ptr(self.T0), self.dt,
+            self.rtol, self.atol, _ptr(self.lm), self.max_steps, _ptr(gY), _ptr(gE), _ptr(grad),
+            _ptr(self.status), _ptr(self.ws), self.ws.numel(), self._stream())
+        _lib.check(rc, "burn_batch_adjoint_backward")
+        return grad
+
+
+class BurnFn(torch.autograd.Function):
+    """(Y_end[N, C], E[C]) of a burn as a differentiable function of the
+    network-global log-rate multipliers p[R]; the backward pass is the
+    discrete adjoint and returns dL/dp summed over the cells.
+
+        Y, E = BurnFn.apply(p, net, Y0, rho, T0, dt, rtol, atol, max_steps)
+    """
+
+    @staticmethod
+    def forward(ctx, log_mult, net, Y0, rho, T0, dt, rtol=1e-6, atol=1e-10, max_steps=2048):
+        run = AdjointRun(net, Y0, rho, T0, dt, rtol, atol, log_mult.detach(),
+                         max_steps=max_steps, device=log_mult.device)
+        Y, T, E, status = run.forward()
+        ctx.run = run
+        ctx.mark_non_differentiable(status)
+        return Y.clone(), E.clone(), status
+
+    @staticmethod
+    def backward(ctx, gY, gE, _gstatus):
+        run = ctx.run
+        if gY is None:
+            gY = torch.zeros_like(run.Y)
+        if gE is None:
+            gE = torch.zeros_like(run.E)
+        grad = run.backward(gY.contiguous(), gE.contiguous())
+        return grad.sum(dim=1), None, None, None, None, None, None, None, None

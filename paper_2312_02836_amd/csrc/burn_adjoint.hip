@@ -1,0 +1,616 @@
+// burn_adjoint.hip -- sensitivities of the burn with respect to the
+// per-reaction log-rate multipliers p_r (the rate-sensitivity question the
+// paper raises in Sec. 1), by a discrete adjoint.
+//
+// What is differentiated: the burn replayed on its own frozen schedule.  A
+// recording run (the production integrator, REC mode) stores for every
+// accepted step its BDF order k_n, step size h_n and the product rho_n of the
+// history rescale ratios applied since the previous accepted step (all at
+// order k_n), plus the initial step size.  The replay then takes, per step,
+//   D <- rescale(D, k_n, rho_n); y0 = sum_{j<=k} D_j;
+//   psi = sum_{j=1..k} gamma_j D_j / gamma_k;  c = h_n / gamma_k;
+//   d solves d + psi - c f(y0 + d; p) = 0 exactly (full Newton to 1e-10);
+//   D_{k+1} = d; D_j += D_{j+1} (j = k..0),
+// starting from D_0 = y(0), D_1 = h_init f(y(0)), and y_end = D_0 (the
+// integrator's row D_{k+2} only feeds error estimates, i.e. the frozen
+// decisions, so it drops out of the map).  Every
+// operation but the corrector is linear in D with schedule-only
+// coefficients, so the reverse sweep is: transpose of the update, then the
+// corrector's adjoint mu = M^-T lambda_d with M = I - c J(y_new),
+// contributing c J^T mu to y0, -mu to psi and c R_r (sum_i W_ir mu_i) to
+// dL/dp_r (W = nu for a species, q_r / c_v for temperature), then the
+// transposes of the predictor, psi and the rescale.
+//
+// Memory: the schedule and a checkpoint of D every CK steps live in a
+// caller-provided workspace; the reverse sweep recomputes each CK-step
+// segment forward from its checkpoint, keeping the corrected states of the
+// segment in LDS, and walks it backwards.
+//
+// Mapping: one cell per wave, lane i = component i (n <= 64); the Newton
+// matrix sits in LDS, one row per lane, and is factored there with
+// row-position tracking; reactions are spread over the lanes.
+
+#include "burn_body.h"
+
+namespace bn {
+namespace {
+
+constexpr int CK = 16;          // accepted steps per checkpoint segment
+constexpr int ADJ_MAXIT = 8;    // full-Newton iterations of the exact corrector
+constexpr double ADJ_TOL = 1e-10;
+constexpr int GR = 4;           // reactions per lane in the gradient (R <= 256)
+
+// ---------------------------------------------------------------------------
+// Recording run: the plain kernel with the schedule recorder.
+
+template <int L, int S, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
+burn_record_kernel(BurnArgs a, int block_waves) {
+  using SH = Shape<L, S>;
+  extern __shared__ double smem[];
+  load_tables(a.net, a.log_mult, smem);
+  __syncthreads();
+  const Tabs tb = tabs_at(smem, a.net.R);
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double *wb = smem + tab_doubles_of(a.net.R) + (size_t)wave * SH::wave_doubles(a.net.n);
+  const int64_t first = ((int64_t)blockIdx.x * block_waves + wave) * SH::CPW + lane / L;
+  run_cells<L, S, false, true>(a, tb, wb, first, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Replay / adjoint kernel.
+
+// LDS doubles per wave for a system of size n.
+__host__ __device__ inline size_t adj_wave_doubles(int n) {
+  const int ms = n | 1;
+  return 64 * 6 + (size_t)n * ms + (size_t)CK * n;
+}
+
+// Rate of reaction r at the state in ybuf (T-powers given) and its
+// derivatives with respect to the reactant slots (g[0..2]) and T (g[3]).
+struct TPow {
+  double T, t13, tm13, t53, lnT, tinv;
+};
+
+__device__ __forceinline__ TPow tpow(double T) {
+  TPow p;
+  p.T = T;
+  p.t13 = cbrt(T);
+  p.tm13 = 1.0 / p.t13;
+  p.t53 = T * p.t13 * p.t13;
+  p.lnT = log(T);
+  p.tinv = 1.0 / T;
+  return p;
+}
+
+__device__ __forceinline__ double rate_and_slots(const Tabs &tb, int r, const TPow &tp,
+                                                 const double *ybuf, double rho, bool want_g,
+                                                 double g[4]) {
+  const double *c = tb.rtab + 8 * (size_t)r;
+  const double expo = c[0] + c[1] * tp.tinv + c[2] * tp.tm13 + c[3] * tp.t13 + c[4] * tp.T +
+                      c[5] * tp.t53 + c[6] * tp.lnT;
+  const int *sp = tb.rsp + 4 * r;
+  double pre = exp(expo) * tb.emult[r] * c[7];
+  for (int i = 1; i < sp[3]; ++i) pre *= rho;
+  const double ya = sp[0] >= 0 ? ybuf[sp[0]] : 1.0;
+  const double yb = sp[1] >= 0 ? ybuf[sp[1]] : 1.0;
+  const double yc = sp[2] >= 0 ? ybuf[sp[2]] : 1.0;
+  double full = pre;
+  if (sp[0] >= 0) full *= ya;
+  if (sp[1] >= 0) full *= yb;
+  if (sp[2] >= 0) full *= yc;
+  if (want_g) {
+    const double dl = -c[1] * tp.tinv * tp.tinv - (1.0 / 3.0) * c[2] * tp.tm13 * tp.tinv +
+                      (1.0 / 3.0) * c[3] * tp.t13 * tp.tinv + c[4] +
+                      (5.0 / 3.0) * c[5] * tp.t13 * tp.t13 + c[6] * tp.tinv;
+    g[0] = pre;
+    g[1] = pre;
+    g[2] = pre;
+    g[3] = full * dl;
+    if (sp[1] >= 0) g[0] *= yb;
+    if (sp[2] >= 0) g[0] *= yc;
+    if (sp[0] >= 0) g[1] *= ya;
+    if (sp[2] >= 0) g[1] *= yc;
+    if (sp[0] >= 0) g[2] *= ya;
+    if (sp[1] >= 0) g[2] *= yb;
+  }
+  return full;
+}
+
+__device__ __forceinline__ void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// One cell per wave.  BACKWARD = false: replay from y(0), write the
+// checkpoints, the end state and E.  BACKWARD = true: reverse sweep.
+template <bool BACKWARD>
+__global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
+  extern __shared__ double smem[];
+  load_tables(a.net, a.log_mult, smem);
+  __syncthreads();
+  const Tabs tb = tabs_at(smem, a.net.R);
+  const NetTables &nt = a.net;
+  const int N = nt.N, R = nt.R, n = nt.n;
+  const int MS = n | 1;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t cell = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (cell >= a.n_cells) return;  // whole wave: no later workgroup barrier
+
+  double *wb = smem + tab_doubles_of(R) + (size_t)wave * adj_wave_doubles(n);
+  double *ybuf = wb;
+  double *facc = wb + 64;
+  double *vbuf = wb + 128;
+  double *jout = wb + 192;
+  double *dinvp = wb + 256;
+  int *prow = reinterpret_cast<int *>(wb + 320);
+  double *M = wb + 384;
+  double *seg = M + (size_t)n * MS;
+
+  const int64_t C = a.n_cells;
+  const bool own = lane < n;  // lane owns component `lane`
+  const double rho = a.rho[cell];
+  const double *blk = a.sched + cell * a.sched_stride;
+  const int n_steps = (int)blk[0];
+  const double *sh = blk + 2;
+  const double *sr = blk + 2 + a.sched_cap;
+  const int32_t *so = reinterpret_cast<const int32_t *>(blk + 2 + 2 * (int64_t)a.sched_cap);
+  double *ck = a.ckpt + (size_t)cell * a.n_ckpt * 7 * n;
+
+  // a failed recording run (or, backward, a failed replay): no replay
+  const int st_in = a.status[cell];
+  if (n_steps < 0 || st_in != ST_OK) {
+    if constexpr (BACKWARD) {
+      for (int r = lane; r < R; r += 64) a.grad[(int64_t)r * C + cell] = 0.0;
+    } else {
+      if (lane == 0) a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
+    }
+    return;
+  }
+
+  // initial state
+  double y0v = 0.0;
+  if (own) y0v = (lane < N) ? a.Y0[(int64_t)lane * C + cell] : a.T0[cell];
+
+  // ---- wave-level building blocks ----
+  // F = f(y) into facc (species rows) + heat; the Newton matrix I - cJ(y)
+  // into M.  y is taken from ybuf.  Returns 1 if everything is finite.
+  auto eval_f_m = [&](double c, bool want_f, bool want_m, double &f_out) -> int {
+    if (want_f && own) facc[lane] = 0.0;
+    if (want_m && own)
+      for (int j = 0; j < n; ++j) M[lane * MS + j] = (lane == j) ? 1.0 : 0.0;
+    wave_lds_sync();
+    const TPow tp = tpow(ybuf[N]);
+    double heat = 0.0;
+    int bad = 0;
+    for (int r = lane; r < R; r += 64) {
+      double g[4];
+      const double v = rate_and_slots(tb, r, tp, ybuf, rho, want_m, g);
+      const int4 *ro = reinterpret_cast<const int4 *>(tb.rout + 8 * r);
+      const int4 r0 = ro[0], r1 = ro[1];
+      const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+      if (want_f) {
+        heat += tb.q[r] * v;
+        for (int e = 0; e < r0.x; ++e)
+          lds_add(&facc[ent[e] >> 8], (double)(signed char)(ent[e] & 0xff) * v);
+      }
+      if (want_m) {
+        const int *sp = tb.rsp + 4 * r;
+        const double qc = tb.qcv[r];
+        for (int s = 0; s < 4; ++s) {
+          const int col = (s < 3) ? sp[s] : N;
+          if (col < 0) continue;
+          if (!isfinite(g[s])) bad = 1;
+          const double val = -c * g[s];
+          for (int e = 0; e < r0.x; ++e)
+            lds_add(&M[(ent[e] >> 8) * MS + col], (double)(signed char)(ent[e] & 0xff) * val);
+          lds_add(&M[N * MS + col], qc * val);
+        }
+      }
+    }
+    heat = gsum<64>(heat);
+    wave_lds_sync();
+    f_out = 0.0;
+    if (want_f && own) f_out = (lane < N) ? facc[lane] : heat * nt.inv_cv;
+    if (own && !isfinite(f_out)) bad = 1;
+    return !gor<64>(bad);
+  };
+
+  // LU of M in place (rows stay put; prow[p] = physical row at position p,
+  // dinvp[p] = 1/U_pp).  Returns 1 if nonsingular.
+  auto factor = [&]() -> int {
+    int pos = lane;
+    int sing = 0;
+    double fdinv = 1.0;
+    double *Mrow = M + (own ? lane : 0) * MS;
+    for (int K = 0; K < n; ++K) {
+      double v = -2.0;
+      int nan_k = 0;
+      const bool cand = own && pos >= K;
+      if (cand) {
+        v = fabs(Mrow[K]);
+        if (v != v) {
+          if (pos == K) nan_k = 1;
+          v = -1.0;
+        }
+      }
+      int bp = cand ? pos : (1 << 30);
+      int prow_i = lane;
+      gargmax3<64>(v, bp, prow_i);
+      nan_k = gor<64>(nan_k);
+      if (!(v > 0.0) || nan_k) sing = 1;
+      if (own) {
+        if (pos == K) pos = bp;
+        else if (pos == bp) pos = K;
+      }
+      const double *P = M + prow_i * MS;
+      const double rinv = 1.0 / P[K];
+      if (own && pos == K) fdinv = rinv;
+      if (own && pos > K) {
+        const double l = Mrow[K] * rinv;
+        Mrow[K] = l;
+        for (int j = K + 1; j < n; ++j) Mrow[j] -= l * P[j];
+      }
+      wave_lds_sync();
+    }
+    if (own) {
+      prow[pos] = lane;
+      dinvp[pos] = fdinv;
+    }
+    wave_lds_sync();
+    return !sing;
+  };
+
+  // x = M^-1 b (b, x: component `lane`)
+  auto solve = [&](double b) -> double {
+    if (own) vbuf[lane] = b;
+    wave_lds_sync();
+    const int pr = own ? prow[lane] : 0;  // lane works on position `lane`
+    double z = own ? vbuf[pr] : 0.0;
+    const double *Lrow = M + pr * MS;
+    for (int K = 0; K < n; ++K) {
+      const double zk = readlane_f64(z, K);
+      if (own && lane > K) z -= Lrow[K] * zk;
+    }
+    const double dv = own ? dinvp[lane] : 1.0;
+    for (int K = n - 1; K >= 0; --K) {
+      const double xk = readlane_f64(z * dv, K);
+      if (lane == K) z = xk;
+      if (own && lane < K) z -= Lrow[K] * xk;
+    }
+    wave_lds_sync();
+    return z;  // position `lane` = column `lane`
+  };
+
+  // y = M^-T c (c, y: component `lane`)
+  auto solve_t = [&](double cv) -> double {
+    // U^T w = c over positions (lane p holds w_p), then L^T v = w, y = P^T v
+    double w = own ? cv : 0.0;
+    double acc = 0.0;
+    for (int K = 0; K < n; ++K) {
+      const double wk = readlane_f64((w - acc) * (own ? dinvp[lane] : 1.0), K);
+      if (lane == K) w = wk;
+      const int rk = prow[K];
+      if (own && lane > K) acc += M[rk * MS + lane] * wk;
+    }
+    double v = w;
+    for (int K = n - 1; K >= 0; --K) {
+      const double vk = readlane_f64(v, K);
+      const int rk = prow[K];
+      if (own && lane < K) v -= M[rk * MS + lane] * vk;
+    }
+    if (own) vbuf[prow[lane]] = v;
+    wave_lds_sync();
+    const double y = own ? vbuf[lane] : 0.0;
+    wave_lds_sync();
+    return y;
+  };
+
+  auto wrms = [&](double v, double inv) -> double {
+    const double z = own ? v * inv : 0.0;
+    return sqrt(gsum<64>(z * z) / (double)n);
+  };
+
+  // history rows of this lane's component
+  double D[DROWS];
+#pragma unroll
+  for (int j = 0; j < DROWS; ++j) D[j] = 0.0;
+
+  auto rescale_fwd = [&](int k, double rh) {
+    double v[KMAX + 1];
+#pragma unroll
+    for (int m = 0; m <= KMAX; ++m) {
+      const double x = (double)m * rh;
+      double rb = 1.0, acc = D[0];
+#pragma unroll
+      for (int b = 1; b <= KMAX; ++b) {
+        rb *= ((double)(b - 1) - x) * (1.0 / (double)b);
+        if (b <= k) acc += rb * D[b];
+      }
+      v[m] = acc;
+    }
+#pragma unroll
+    for (int aa = 0; aa <= KMAX; ++aa) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m <= aa; ++m)
+        if (m <= k) acc += u_of(m, aa) * v[m];
+      if (aa <= k) D[aa] = acc;
+    }
+  };
+
+  // the replay of one accepted step; returns the corrected state in y_new
+  // (this lane's component); 0 on a non-finite or singular corrector
+  auto replay_step = [&](int m, double &y_new) -> int {
+    const int k = so[m];
+    const double hstep = sh[m], ratio = sr[m];
+    if (ratio != 1.0) rescale_fwd(k, ratio);
+    double gk = 1.0;
+#pragma unroll
+    for (int kk = 1; kk <= KMAX; ++kk)
+      if (kk == k) gk = gamma_of(kk);
+    double ypred = D[0], sb = 0.0;
+#pragma unroll
+    for (int j = 1; j <= KMAX; ++j)
+      if (j <= k) {
+        ypred += D[j];
+        sb += gamma_of(j) * D[j];
+      }
+    const double psi = sb / gk;
+    const double isc = 1.0 / (a.atol + a.rtol * fabs(ypred));
+    const double c = hstep / gk;
+    double d = 0.0, y = ypred;
+    int ok = 1;
+    for (int it = 0; it < ADJ_MAXIT; ++it) {
+      if (own) ybuf[lane] = y;
+      double F;
+      ok = eval_f_m(c, true, true, F);
+      if (!ok) break;
+      if (!factor()) {
+        ok = 0;
+        break;
+      }
+      const double dy = solve(c * F - psi - d);
+      const double dn = wrms(dy, isc);
+      if (!isfinite(dn)) {
+        ok = 0;
+        break;
+      }
+      y += dy;
+      d += dy;
+      if (dn <= ADJ_TOL) break;
+    }
+    y_new = y;
+    // history update (row k+2 of the production integrator only feeds its
+    // error estimates, never the solution, so the replay does not keep it)
+#pragma unroll
+    for (int kk = 1; kk <= KMAX; ++kk) {
+      if (kk == k) {
+        D[kk + 1] = d;
+#pragma unroll
+        for (int j = kk; j >= 0; --j) D[j] += D[j + 1];
+      }
+    }
+    return ok;
+  };
+
+  // ---------------- forward replay from y(0) ----------------
+  auto init_history = [&]() -> int {
+    if (own) ybuf[lane] = y0v;
+    double f0;
+    const int ok = eval_f_m(0.0, true, false, f0);
+#pragma unroll
+    for (int j = 0; j < DROWS; ++j) D[j] = 0.0;
+    D[0] = y0v;
+    D[1] = blk[1] * f0;
+    return ok;
+  };
+
+  if constexpr (!BACKWARD) {
+    int ok = init_history();
+    double y_new = 0.0;
+    for (int m = 0; m < n_steps && ok; ++m) {
+      if (m % CK == 0 && own) {
+        double *cp = ck + (size_t)(m / CK) * 7 * n;
+#pragma unroll
+        for (int j = 0; j < DROWS; ++j) cp[j * n + lane] = D[j];
+      }
+      ok = replay_step(m, y_new);
+    }
+    if (!ok) {
+      if (lane == 0) a.status[cell] = ST_NONFINITE;
+      return;
+    }
+    if (own) {
+      if (lane < N) a.Yout[(int64_t)lane * C + cell] = D[0];
+      else {
+        a.Tout[cell] = D[0];
+        a.Eout[cell] = (D[0] - y0v) / nt.inv_cv;
+      }
+    }
+  } else {
+    // ---------------- reverse sweep ----------------
+    // cotangent of y_end: (gY, c_v gE) on D_0
+    double lam[DROWS];
+#pragma unroll
+    for (int j = 0; j < DROWS; ++j) lam[j] = 0.0;
+    if (own) lam[0] = (lane < N) ? a.gY[(int64_t)lane * C + cell] : a.gE[cell] / nt.inv_cv;
+    double gr[GR];
+#pragma unroll
+    for (int u = 0; u < GR; ++u) gr[u] = 0.0;
+
+    // per reaction: w_r = sum_i W_ir mu_i with mu in vbuf; adds
+    // scale * R_r * w_r to the gradient and, if want_jt, scale * w_r * dR_r/dy
+    // into jout (J^T mu).  The state is in ybuf.
+    auto accumulate = [&](double scale, bool want_jt) {
+      if (want_jt && own) jout[lane] = 0.0;
+      wave_lds_sync();
+      const TPow tp = tpow(ybuf[N]);
+      for (int u = 0; u < GR; ++u) {
+        const int r = lane + 64 * u;
+        if (r >= R) break;
+        double g[4];
+        const double v = rate_and_slots(tb, r, tp, ybuf, rho, want_jt, g);
+        const int4 *ro = reinterpret_cast<const int4 *>(tb.rout + 8 * r);
+        const int4 r0 = ro[0], r1 = ro[1];
+        const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+        double w = tb.qcv[r] * vbuf[N];
+        for (int e = 0; e < r0.x; ++e) w += (double)(signed char)(ent[e] & 0xff) * vbuf[ent[e] >> 8];
+        gr[u] += scale * v * w;
+        if (want_jt) {
+          const int *sp = tb.rsp + 4 * r;
+          for (int s = 0; s < 4; ++s) {
+            const int col = (s < 3) ? sp[s] : N;
+            if (col >= 0) lds_add(&jout[col], w * g[s]);
+          }
+        }
+      }
+      wave_lds_sync();
+    };
+
+    const int n_seg = (n_steps + CK - 1) / CK;
+    for (int sg = n_seg - 1; sg >= 0; --sg) {
+      const int m0 = sg * CK;
+      const int m1 = (m0 + CK < n_steps) ? m0 + CK : n_steps;
+      // recompute the segment from its checkpoint, keeping y_new
+      if (own) {
+        const double *cp = ck + (size_t)sg * 7 * n;
+#pragma unroll
+        for (int j = 0; j < DROWS; ++j) D[j] = cp[j * n + lane];
+      }
+      for (int m = m0; m < m1; ++m) {
+        double y_new;
+        replay_step(m, y_new);
+        if (own) seg[(m - m0) * n + lane] = y_new;
+      }
+      // walk it backwards
+      for (int m = m1 - 1; m >= m0; --m) {
+        const int k = so[m];
+        const double ratio = sr[m];
+        double gk = 1.0;
+#pragma unroll
+        for (int kk = 1; kk <= KMAX; ++kk)
+          if (kk == k) gk = gamma_of(kk);
+        const double c = sh[m] / gk;
+        // transpose of the history update D'_{k+1} = d, D'_j = sum_{i=j..k} D_i + d
+        double pre[DROWS];
+        double run = 0.0;
+#pragma unroll
+        for (int j = 0; j < DROWS; ++j) {
+          run += lam[j];
+          pre[j] = run;  // sum_{i<=j} lam_i
+        }
+        double ld = 0.0;
+#pragma unroll
+        for (int kk = 1; kk <= KMAX; ++kk)
+          if (kk == k) {
+            ld = pre[kk] + lam[kk + 1];
+#pragma unroll
+            for (int j = 0; j <= kk; ++j) lam[j] = pre[j];
+            lam[kk + 1] = 0.0;
+          }
+        // corrector: mu = M^-T lambda_d at y_new
+        if (own) ybuf[lane] = seg[(m - m0) * n + lane];
+        double dummy;
+        eval_f_m(c, false, true, dummy);
+        factor();
+        const double mu = solve_t(ld);
+        if (own) vbuf[lane] = mu;
+        accumulate(c, true);
+        const double ly0 = own ? c * jout[lane] : 0.0;
+        const double lpsi = -mu;
+#pragma unroll
+        for (int j = 0; j <= KMAX; ++j)
+          if (j <= k) lam[j] += ly0;
+#pragma unroll
+        for (int j = 1; j <= KMAX; ++j)
+          if (j <= k) lam[j] += (gamma_of(j) / gk) * lpsi;
+        // transpose of the rescale: lam <- (R(rho) U) lam on rows 0..k
+        if (ratio != 1.0) {
+          double w[KMAX + 1];
+#pragma unroll
+          for (int mm = 0; mm <= KMAX; ++mm) {
+            double acc = 0.0;
+#pragma unroll
+            for (int aa = mm; aa <= KMAX; ++aa)
+              if (aa <= k) acc += u_of(mm, aa) * lam[aa];
+            w[mm] = acc;
+          }
+          double nl[KMAX + 1];
+#pragma unroll
+          for (int b = 0; b <= KMAX; ++b) nl[b] = 0.0;
+#pragma unroll
+          for (int mm = 0; mm <= KMAX; ++mm) {
+            if (mm > k) continue;
+            const double x = (double)mm * ratio;
+            double rb = 1.0;
+            nl[0] += w[mm];
+#pragma unroll
+            for (int b = 1; b <= KMAX; ++b) {
+              rb *= ((double)(b - 1) - x) * (1.0 / (double)b);
+              if (b <= k) nl[b] += rb * w[mm];
+            }
+          }
+#pragma unroll
+          for (int b = 0; b <= KMAX; ++b)
+            if (b <= k) lam[b] = nl[b];
+        }
+      }
+    }
+    // D_1 = h_init f(y(0)): its multiplier dependence
+    if (own) {
+      ybuf[lane] = y0v;
+      vbuf[lane] = lam[1];
+    }
+    accumulate(blk[1], false);
+    for (int u = 0; u < GR; ++u) {
+      const int r = lane + 64 * u;
+      if (r < R) a.grad[(int64_t)r * C + cell] = gr[u];
+    }
+  }
+}
+
+}  // namespace
+
+size_t adjoint_sched_stride(int cap) { return 2 + 2 * (size_t)cap + ((size_t)cap + 1) / 2; }
+int adjoint_n_ckpt(int cap) { return (cap + CK - 1) / CK; }
+size_t adjoint_lds_bytes(int R, int n, int waves) {
+  return 8 * (tab_doubles_of(R) + (size_t)waves * adj_wave_doubles(n));
+}
+
+hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
+#define BN_REC(l, s)                                                                          \
+  if (L == l && S == s) {                                                                      \
+    using SH = Shape<l, s>;                                                                    \
+    const size_t lds =                                                                         \
+        8 * (tab_doubles_of(a.net.R) + (size_t)block_waves * SH::wave_doubles(a.net.n));       \
+    const int64_t per = (int64_t)SH::CPW * block_waves;                                        \
+    const int64_t blocks = (a.n_cells + per - 1) / per;                                        \
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;                                      \
+    hipLaunchKernelGGL((burn_record_kernel<l, s, 1>), dim3((unsigned)blocks),                  \
+                       dim3(64 * block_waves), lds, stream, a, block_waves);                   \
+    return hipGetLastError();                                                                  \
+  }
+  BN_REC(4, 4)
+  BN_REC(16, 2)
+  BN_REC(32, 1)
+  BN_REC(64, 1)
+#undef BN_REC
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_t stream) {
+  const size_t lds = adjoint_lds_bytes(a.net.R, a.net.n, waves);
+  const int64_t blocks = (a.n_cells + waves - 1) / waves;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (backward)
+    hipLaunchKernelGGL((adjoint_kernel<true>), dim3((unsigned)blocks), dim3(64 * waves), lds,
+                       stream, a);
+  else
+    hipLaunchKernelGGL((adjoint_kernel<false>), dim3((unsigned)blocks), dim3(64 * waves), lds,
+                       stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace bn

@@ -612,4 +612,187 @@ int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
   return BN_SUCCESS;
 }
 
+
+// ---- sensitivities -------------------------------------------------------
+
+namespace {
+
+struct AdjLayout {
+  size_t stride;      // schedule doubles per cell
+  int n_ckpt;
+  size_t sched_bytes, ckpt_bytes, total;
+};
+
+AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
+  AdjLayout l{};
+  l.stride = bn::adjoint_sched_stride(cap);
+  l.n_ckpt = bn::adjoint_n_ckpt(cap);
+  l.sched_bytes = 8 * l.stride * (size_t)n_cells;
+  l.ckpt_bytes = 8 * (size_t)n_cells * l.n_ckpt * 7 * (size_t)net->n;
+  l.total = l.sched_bytes + l.ckpt_bytes;
+  return l;
+}
+
+int adj_check(const bn_network *net, int64_t n_cells, double dt, double rtol, double atol,
+              int32_t max_steps, void *workspace, size_t workspace_bytes, int *dev_out) {
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (n_cells < 0) return fail(BN_EINVAL, "n_cells < 0");
+  if (int rc = check_tol(dt, rtol, atol)) return rc;
+  if (max_steps < 1 || max_steps > 1000000)
+    return fail(BN_EINVAL, "max_steps must be 1..1000000 for sensitivity runs");
+  if (net->R > BN_ADJOINT_MAX_REACTIONS)
+    return fail(BN_EUNSUPPORTED, "more reactions than BN_ADJOINT_MAX_REACTIONS");
+  if (n_cells == 0) return BN_SUCCESS;
+  const AdjLayout l = adj_layout(net, n_cells, max_steps);
+  if (!workspace || workspace_bytes < l.total)
+    return fail(BN_EINVAL, "workspace missing or smaller than burn_batch_adjoint_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % 8) return fail(BN_EINVAL, "workspace not 8-byte aligned");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  if (bn::adjoint_lds_bytes(net->R, net->n, 1) > lim.lds_block)
+    return fail(BN_EUNSUPPORTED, "network too large for the adjoint kernel's LDS");
+  *dev_out = dev;
+  return BN_SUCCESS;
+}
+
+bn::AdjArgs adj_args(const bn_network *net, int64_t n_cells, const double *state0,
+                     const double *rho, const double *T0, double rtol, double atol,
+                     const double *log_mult, int32_t max_steps, int32_t *status,
+                     void *workspace) {
+  const AdjLayout l = adj_layout(net, n_cells, max_steps);
+  bn::AdjArgs a{};
+  a.net = net->tables;
+  a.n_cells = n_cells;
+  a.Y0 = state0;
+  a.rho = rho;
+  a.T0 = T0;
+  a.log_mult = log_mult;
+  a.status = status;
+  a.sched = static_cast<double *>(workspace);
+  a.sched_stride = (int64_t)l.stride;
+  a.sched_cap = max_steps;
+  a.ckpt = reinterpret_cast<double *>(static_cast<char *>(workspace) + l.sched_bytes);
+  a.n_ckpt = l.n_ckpt;
+  a.rtol = rtol;
+  a.atol = atol;
+  return a;
+}
+
+// waves per workgroup of the adjoint kernels: as many (<= 4) as LDS allows
+int adj_waves(const bn_network *net) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  DeviceLimits lim;
+  if (device_limits(dev, &lim)) return 1;
+  int w = 4;
+  while (w > 1 && bn::adjoint_lds_bytes(net->R, net->n, w) > lim.lds_block) w /= 2;
+  return w;
+}
+
+}  // namespace
+
+size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells,
+                                          int32_t max_steps) {
+  if (!net || n_cells < 0 || max_steps < 1) return 0;
+  return adj_layout(net, n_cells, max_steps).total;
+}
+
+int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const double *state0,
+                               const double *rho, const double *T0, double dt, double rtol,
+                               double atol, const double *log_mult, int32_t max_steps,
+                               double *state_out, double *T_out, double *E_out,
+                               int32_t *status, int32_t *counters, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+  g_err.clear();
+  int dev = -1;
+  if (int rc = adj_check(net, n_cells, dt, rtol, atol, max_steps, workspace, workspace_bytes,
+                         &dev))
+    return rc;
+  if (n_cells == 0) return BN_SUCCESS;
+  if (!state0 || !rho || !T0 || !state_out || !T_out || !E_out || !status)
+    return fail(BN_EINVAL, "null array argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the recording run works on the output arrays
+  if (hipMemcpyAsync(state_out, state0, 8 * (size_t)net->N * n_cells, hipMemcpyDeviceToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(T_out, T0, 8 * (size_t)n_cells, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(BN_EHIP, "hipMemcpyAsync of the initial state failed");
+  int L = net->L, S = net->S;
+  if (!L || multi_shape_index(L, S) < 0) default_multi_shape(net->n, &L, &S);
+  bn::BurnArgs b{};
+  b.net = net->tables;
+  b.n_cells = n_cells;
+  b.Y = state_out;
+  b.rho = rho;
+  b.T = T_out;
+  b.log_mult = log_mult;
+  b.status = status;
+  b.counters = counters;
+  b.t_end = dt;
+  b.rtol = rtol;
+  b.atol = atol;
+  b.max_steps = max_steps;
+  bn::AdjArgs a = adj_args(net, n_cells, state0, rho, T0, rtol, atol, log_mult, max_steps, status,
+                           workspace);
+  b.sched = a.sched;
+  b.sched_stride = a.sched_stride;
+  b.sched_cap = a.sched_cap;
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  int bw = 2;
+  while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) --bw;
+  if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
+    return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
+  hipError_t e = bn::launch_record(b, L, S, bw, st);
+  if (e != hipSuccess) return fail(BN_EHIP, std::string("recording launch failed: ") + hipGetErrorString(e));
+  a.Yout = state_out;
+  a.Tout = T_out;
+  a.Eout = E_out;
+  e = bn::launch_adjoint(a, false, adj_waves(net), st);
+  if (e != hipSuccess) return fail(BN_EHIP, std::string("replay launch failed: ") + hipGetErrorString(e));
+  return BN_SUCCESS;
+}
+
+int burn_batch_adjoint_backward(const bn_network *net, int64_t n_cells, const double *state0,
+                                const double *rho, const double *T0, double dt, double rtol,
+                                double atol, const double *log_mult, int32_t max_steps,
+                                const double *gY, const double *gE, double *grad,
+                                const int32_t *status, void *workspace, size_t workspace_bytes,
+                                void *stream) {
+  g_err.clear();
+  int dev = -1;
+  if (int rc = adj_check(net, n_cells, dt, rtol, atol, max_steps, workspace, workspace_bytes,
+                         &dev))
+    return rc;
+  if (n_cells == 0) return BN_SUCCESS;
+  if (!state0 || !rho || !T0 || !gY || !gE || !grad || !status)
+    return fail(BN_EINVAL, "null array argument");
+  bn::AdjArgs a = adj_args(net, n_cells, state0, rho, T0, rtol, atol, log_mult, max_steps,
+                           const_cast<int32_t *>(status), workspace);
+  a.gY = gY;
+  a.gE = gE;
+  a.grad = grad;
+  const hipError_t e = bn::launch_adjoint(a, true, adj_waves(net), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(BN_EHIP, std::string("adjoint launch failed: ") + hipGetErrorString(e));
+  return BN_SUCCESS;
+}
+
+int burn_batch_adjoint(const bn_network *net, int64_t n_cells, const double *state0,
+                       const double *rho, const double *T0, double dt, double rtol, double atol,
+                       const double *log_mult, int32_t max_steps, const double *gY,
+                       const double *gE, double *state_out, double *T_out, double *E_out,
+                       double *grad, int32_t *status, int32_t *counters, void *workspace,
+                       size_t workspace_bytes, void *stream) {
+  int rc = burn_batch_adjoint_forward(net, n_cells, state0, rho, T0, dt, rtol, atol, log_mult,
+                                      max_steps, state_out, T_out, E_out, status, counters,
+                                      workspace, workspace_bytes, stream);
+  if (rc != BN_SUCCESS) return rc;
+  return burn_batch_adjoint_backward(net, n_cells, state0, rho, T0, dt, rtol, atol, log_mult,
+                                     max_steps, gY, gE, grad, status, workspace, workspace_bytes,
+                                     stream);
+}
+
 }  // extern "C"

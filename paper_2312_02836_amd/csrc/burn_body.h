@@ -302,8 +302,10 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
 // first_cell for this lane group, then nothing) or, when queue is not null,
 // from a device work queue: a group whose cell has finished writes it out and
 // takes the next index from the queue, until the queue passes n_cells.  The
-// loop ends when every group of the wave is idle.
-template <int L, int S, bool QUEUE>
+// loop ends when every group of the wave is idle.  With REC the accepted
+// steps' schedule (order, step size, product of the history rescale ratios
+// since the previous accepted step) is recorded for a sensitivity replay.
+template <int L, int S, bool QUEUE, bool REC = false>
 __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, double *wb,
                                           int64_t first_cell, unsigned long long *queue) {
   using SH = Shape<L, S>;
@@ -363,7 +365,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 
   // change of step size by ratio rh on rows 0..k of D: D <- (R(rh) U)^T D,
   // applied in its two factors (values at the new nodes, then differences)
+  double racc = 1.0;  // rescale ratios since the last accepted step (REC)
   auto rescale = [&](int k, double rh) __attribute__((always_inline)) {
+    if constexpr (REC) racc *= rh;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int i = comp(s);
@@ -501,6 +505,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         if (i < N) a.Y[(int64_t)i * C + cell] = Dl[i];
         else if (i == N) a.T[cell] = Dl[i];
       }
+    }
+    if constexpr (REC) {
+      if (q == 0)
+        a.sched[cell * a.sched_stride] = (status == ST_OK) ? (double)cnt[CNT_STEPS] : -1.0;
     }
     if (q == 0) {
       if (a.status) a.status[cell] = status;
@@ -904,6 +912,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         need_attempt = 1;
         new_step = 1;
         write_state = 1;
+        if constexpr (REC) {
+          racc = 1.0;
+          if (q == 0) a.sched[cell * a.sched_stride + 1] = h;
+        }
         phase = PH_NEWTON;
       } else {  // PH_NEWTON: one modified-Newton iteration
         int fail = !okf;
@@ -985,6 +997,16 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             }
             jac_cur = 0;
             n_eq++;
+            if constexpr (REC) {
+              const int m = cnt[CNT_STEPS];
+              if (q == 0 && m < a.sched_cap) {
+                double *blk = a.sched + cell * a.sched_stride;
+                blk[2 + m] = h;
+                blk[2 + a.sched_cap + m] = racc;
+                reinterpret_cast<int32_t *>(blk + 2 + 2 * (int64_t)a.sched_cap)[m] = k;
+              }
+              racc = 1.0;
+            }
             cnt[CNT_STEPS]++;
             if (n_eq >= k + 1) {
               em_acc = gsum<L>(em_acc);

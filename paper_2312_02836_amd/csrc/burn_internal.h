@@ -42,6 +42,14 @@ struct BurnArgs {
   int32_t *counters;  // [8][n_cells] or nullptr
   double t_end, rtol, atol;
   int max_steps;
+  // Schedule recording (sensitivity runs; nullptr otherwise): per cell a
+  // block of sched_stride doubles at sched + cell * sched_stride holding
+  // [0] accepted steps (-1 if the cell failed), [1] initial step size,
+  // [2, 2 + cap) step sizes, [2 + cap, 2 + 2 cap) rescale ratios, then cap
+  // int32 orders.
+  double *sched;
+  int64_t sched_stride;
+  int sched_cap;
 };
 
 // Shapes (lanes per cell L, slots per lane S; the system is padded to
@@ -77,6 +85,29 @@ struct MultiArgs {
   size_t wave_doubles;            // LDS doubles per wave area (max over items)
 };
 hipError_t launch_multi(const MultiArgs &m, int grid, hipStream_t stream);
+
+// Sensitivity runs (discrete adjoint with respect to the log-rate
+// multipliers).  The replay / adjoint kernels take one cell per wave.
+struct AdjArgs {
+  NetTables net;
+  int64_t n_cells;
+  const double *Y0, *rho, *T0, *log_mult;
+  double *Yout, *Tout, *Eout;  // replayed end state and released energy (forward)
+  const double *gY, *gE;        // cotangents (backward)
+  double *grad;                 // [R][n_cells] (backward)
+  int32_t *status;              // [n_cells] (forward: read and updated; backward: read)
+  double *sched;                // schedule blocks (see BurnArgs)
+  int64_t sched_stride;
+  int sched_cap;
+  double *ckpt;                 // [n_cells][n_ckpt][7][n]
+  int n_ckpt;
+  double rtol, atol;
+};
+size_t adjoint_sched_stride(int cap);  // doubles per cell
+int adjoint_n_ckpt(int cap);
+size_t adjoint_lds_bytes(int R, int n, int waves);
+hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
+hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_t stream);
 
 // Zero n counters with a kernel (no memset node, so the sequence can be
 // captured into a graph and replayed).

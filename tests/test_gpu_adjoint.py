@@ -1,0 +1,152 @@
+"""The GPU discrete adjoint (through the C ABI) against the oracle's forward
+sensitivities of the same frozen-schedule replay: the replayed end state,
+the per-cell vector-Jacobian products, the autograd wrapper, and the failure
+paths."""
+import numpy as np
+import pytest
+
+from paper_2312_02836_amd import synth
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL = 1e-6, 1e-10
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2312_02836_amd import burn as B
+    return B
+
+
+def _cot(spec, C, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(spec.n_species, C)), rng.normal(size=C)
+
+
+def _run_gpu(B, spec, cells, t_end, gY, gE, log_mult=None, max_steps=2048):
+    import torch
+    net = B.Network(spec)
+    run = B.AdjointRun(net, cells.Y, cells.rho, cells.T, t_end, RTOL, ATOL, log_mult,
+                       max_steps=max_steps)
+    Y, T, E, st = run.forward()
+    grad = run.backward(gY, gE)
+    torch.cuda.synchronize()
+    out = (Y.cpu().numpy(), T.cpu().numpy(), E.cpu().numpy(), st.cpu().numpy(),
+           run.counters.cpu().numpy(), grad.cpu().numpy())
+    net.close()
+    return out
+
+
+def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rtol=1e-6):
+    C = cells.n_cells
+    gY, gE = _cot(spec, C, seed)
+    Yg, Tg, Eg, stg, cntg, gg = _run_gpu(B, spec, cells, t_end, gY, gE, log_mult)
+    onet = oracle.OracleNet(spec)
+    Yo, To, sto, cnto, S, unc = oracle.sens(onet, cells, t_end, RTOL, ATOL, log_mult=log_mult)
+
+    def tight(idx):
+        r = oracle.burn(onet, cells.subset(idx), t_end, RTOL * 1e-4, ATOL * 1e-4,
+                        log_mult=log_mult)
+        return r[0], r[1]
+
+    # the replayed end state
+    rep = assert_parity((Yg, Tg, stg, cntg), (Yo, To, sto, cnto), RTOL, ATOL, tight=tight)
+    assert np.allclose(Eg, spec.c_v * (Tg - cells.T), rtol=1e-12, atol=1e-14)
+    # gradients where both sides replayed the same schedule
+    go = oracle.vjp(onet, S, gY, gE)
+    same = rep["same_counters"] & (sto == 0)
+    scale = np.abs(go).max(axis=0)
+    err = np.abs(gg - go).max(axis=0)
+    bad = np.nonzero(same & (err > grad_rtol * scale + 1e-300))[0]
+    print(f"adjoint: cells {C}, same schedule {int(same.sum())}, max rel grad err "
+          f"{(err[same] / np.maximum(scale[same], 1e-300)).max():.3e}", flush=True)
+    assert bad.size == 0, (bad[:10], err[bad[:10]], scale[bad[:10]])
+    assert np.all(gg[:, sto != 0] == 0.0)
+    return gg, go
+
+
+def test_adjoint_synth21(gpu, oracle):
+    """The 21-species / 60-reaction sensitivity workload, 261 cells (a
+    ragged last workgroup)."""
+    cfg = synth.config(5, n_cells=261)
+    _check_adjoint(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end)
+
+
+def test_adjoint_synth13_with_multipliers(gpu, oracle):
+    cfg = synth.config(2, n_cells=130)
+    lm = np.random.default_rng(7).normal(0.0, 0.3, cfg.networks[0].n_reactions)
+    _check_adjoint(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end, seed=1, log_mult=lm)
+
+
+def test_adjoint_synth50(gpu, oracle):
+    """50 species / 150 reactions: one cell per wave with n = 51 lanes."""
+    cfg = synth.config(4, n_cells=33)
+    _check_adjoint(gpu, oracle, cfg.networks[3], cfg.cells[3], cfg.t_end, seed=2)
+
+
+def test_adjoint_bateman_chain(gpu, oracle):
+    """A -> B -> C with heat at tight tolerance: the GPU gradients against the
+    closed-form d(A, B, C, T)/d ln k contracted with the cotangents."""
+    k1, k2, q1, q2, cv = 3.0, 0.7, 1.5, 2.5, 10.0
+    spec = synth.chain_network([k1, k2], q=[q1, q2], c_v=cv)
+    cells = synth.Cells(np.array([[1.0], [0.0], [0.0]]), np.array([1.0]), np.array([2.0]))
+    gY, gE = np.array([[0.3], [-1.2], [0.7]]), np.array([0.5])
+    import torch
+    net = gpu.Network(spec)
+    run = gpu.AdjointRun(net, cells.Y, cells.rho, cells.T, 2.0, 1e-10, 1e-14)
+    run.forward()
+    g = run.backward(gY, gE).cpu().numpy()[:, 0]
+    t = 2.0
+    e1, e2 = np.exp(-k1 * t), np.exp(-k2 * t)
+    dA = np.array([-k1 * t * e1, 0.0])
+    dB = np.array([k1 * (k2 / (k2 - k1) ** 2 * (e1 - e2) - k1 / (k2 - k1) * t * e1),
+                   k2 * (-k1 / (k2 - k1) ** 2 * (e1 - e2) + k1 / (k2 - k1) * t * e2)])
+    dC = -dA - dB
+    dE = -q1 * dA + q2 * dC  # E = c_v dT
+    ref = gY[0, 0] * dA + gY[1, 0] * dB + gY[2, 0] * dC + gE[0] * dE
+    assert np.allclose(g, ref, rtol=1e-6, atol=1e-9), (g, ref)
+    net.close()
+
+
+def test_autograd_function(gpu, oracle):
+    import torch
+    cfg = synth.config(5, n_cells=64)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = gpu.Network(spec)
+    dev = torch.device("cuda", 0)
+    p = torch.zeros(spec.n_reactions, dtype=torch.float64, device=dev, requires_grad=True)
+    Y, E, st = gpu.BurnFn.apply(p, net, cells.Y, cells.rho, cells.T, cfg.t_end)
+    w = torch.linspace(0.5, 1.5, spec.n_species, dtype=torch.float64, device=dev)
+    loss = (w[:, None] * Y).sum() + 0.1 * E.sum()
+    loss.backward()
+    gY = np.broadcast_to(np.linspace(0.5, 1.5, spec.n_species)[:, None], (spec.n_species, 64))
+    onet = oracle.OracleNet(spec)
+    Yo, To, sto, cnto, S, unc = oracle.sens(onet, cells, cfg.t_end)
+    go = oracle.vjp(onet, S, gY, np.full(64, 0.1)).sum(axis=1)
+    gg = p.grad.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    # summed over cells: a few cells may have taken another schedule, so the
+    # bound is on the scale of the whole gradient
+    assert np.allclose(gg, go, rtol=0, atol=1e-6 * np.abs(go).max()), np.abs(gg - go).max()
+    net.close()
+
+
+def test_adjoint_failure_paths(gpu, oracle):
+    cfg = synth.config(5, n_cells=20)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    bad = synth.Cells(cells.Y.copy(), cells.rho.copy(), cells.T.copy())
+    bad.rho[3] = np.nan
+    bad.T[5] = -1.0
+    gY, gE = _cot(spec, 20, 4)
+    Yg, Tg, Eg, stg, cntg, gg = _run_gpu(gpu, spec, bad, cfg.t_end, gY, gE)
+    assert stg[3] == 4 and stg[5] == 4
+    assert np.all(gg[:, [3, 5]] == 0.0) and np.all(Eg[[3, 5]] == 0.0)
+    ok = np.setdiff1d(np.arange(20), [3, 5])
+    assert np.all(stg[ok] == 0)
+    # a step budget smaller than the burn needs
+    Yg, Tg, Eg, stg, cntg, gg = _run_gpu(gpu, spec, cells, cfg.t_end, gY, gE, max_steps=5)
+    assert np.all(stg == 1) and np.all(gg == 0.0)
