@@ -9,7 +9,11 @@ Workloads (--workload):
            in ONE persistent launch with a device work queue; the plain
            kernel (one launch per network, same shapes) is timed beside it;
   synth50  the 50-species / 150-reaction network, 1,048,576 cells, one
-           persistent launch, with the plain launch timed beside it.
+           persistent launch, with the plain launch timed beside it;
+  adjoint21  sensitivities of the 21-species / 60-reaction network, 65,536
+           cells: recording burn, replay with exact correctors and reverse
+           sweep (16-step checkpoints) per step, one random cotangent of all
+           end abundances and E per cell; metric: adjoint grads/s.
 
 A step is one burn of the whole batch from the same initial state (the state
 is restored from a resident copy with device-to-device copies inside the
@@ -43,6 +47,11 @@ WORKLOADS = {
                    text="mixed persistent burn, synthetic 13/30 + 21/60 + 35/100 + 50/150 "
                         "species/reaction networks, {cells} cells each in one launch, dt=1e-2, "
                         "rtol 1e-6, atol 1e-10"),
+    "adjoint21": dict(config=5, cells=65536, mode="adjoint",
+                      text="adjoint sensitivities, synthetic 21-species/60-reaction network, "
+                           "{cells} cells, gradient of all end abundances and E with respect to "
+                           "60 log-rate multipliers, dt=1e-2, rtol 1e-6, atol 1e-10, checkpoint "
+                           "every 16 steps"),
     "synth50": dict(config=3, cells=1048576, mode="persistent",
                     text="persistent burn, synthetic 50-species/150-reaction network, {cells} "
                          "cells, T log-uniform [0.8, 6], dt=1e-2, rtol 1e-6, atol 1e-10"),
@@ -110,6 +119,8 @@ def main() -> int:
     if args.mode:
         wl["mode"] = args.mode
     n_cells = args.cells or wl["cells"]
+    if wl["mode"] == "adjoint":
+        return bench_adjoint(args, wl, n_cells)
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     cfg = synth.config(wl["config"], n_cells=n_cells)
@@ -253,6 +264,105 @@ def main() -> int:
     print(json.dumps(out), flush=True)
     for b in batches:
         b["net"].close()
+    return 0
+
+
+def bench_adjoint(args, wl, n_cells) -> int:
+    import numpy as np
+    import torch
+
+    from paper_2312_02836_amd import burn as B
+    from paper_2312_02836_amd import flops, synth
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    cfg = synth.config(wl["config"], n_cells=n_cells)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = B.Network(spec)
+    run = B.AdjointRun(net, cells.Y, cells.rho, cells.T, cfg.t_end, cfg.rtol, cfg.atol,
+                       max_steps=1024, device=dev)
+    rng = np.random.default_rng(5)
+    gY = torch.as_tensor(rng.normal(size=(spec.n_species, n_cells)), device=dev)
+    gE = torch.as_tensor(rng.normal(size=n_cells), device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        run.forward()
+        return run.backward(gY, gE)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"bench: adjoint: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev0[i].record(stream)
+        run.forward()
+        ev1[i].record(stream)
+        grad = run.backward(gY, gE)
+        ev2[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
+    bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev1, ev2)]))
+    kernel_ms = fwd_ms + bwd_ms
+    ms_per_step = 1000.0 * wall / args.steps
+    st = run.status.cpu().numpy()
+    n_ok = int((st == 0).sum())
+    f_launch = float(flops.adjoint_cell_flops(spec, run.counters.cpu().numpy(),
+                                              run.replay_iters.cpu().numpy())[st == 0].sum())
+    achieved = f_launch / (kernel_ms / 1000.0) / 1e12
+    print(f"bench: adjoint: {args.steps} steps, {ms_per_step:.3f} ms/step (forward {fwd_ms:.3f}, "
+          f"backward {bwd_ms:.3f}), ok {n_ok}/{n_cells}, alg flops/step {f_launch:.4e}",
+          file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        onet = oracle.OracleNet(spec)
+        threads = oracle.max_threads()
+        k = 64
+        rng = np.random.default_rng(1234)
+        while True:
+            idx = np.sort(rng.choice(n_cells, min(k, n_cells), replace=False))
+            tc = time.perf_counter()
+            oracle.sens(onet, cells.subset(idx), cfg.t_end, cfg.rtol, cfg.atol)
+            el = time.perf_counter() - tc
+            if el >= args.cpu_seconds or k >= n_cells:
+                break
+            k = min(n_cells, int(k * max(2.0, 1.2 * args.cpu_seconds / max(el, 1e-3))))
+        cpu = {"value": len(idx) / el, "unit": "grads/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(idx)} seeded random cells of the same workload, forward "
+                         f"sensitivities (all {spec.n_reactions} multipliers), {el:.1f} s on "
+                         f"{threads} OpenMP threads"}
+    out = {
+        "metric": "adjoint grads/s (cell VJPs, FP64, rtol 1e-6)",
+        "value": n_ok / (ms_per_step / 1000.0),
+        "unit": "grads/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["text"].format(cells=n_cells), "cells": n_cells,
+                   "networks": [f"{spec.n_species}/{spec.n_reactions}"], "t_end": cfg.t_end,
+                   "kernel": "adjoint_kernel (+ burn_record_kernel)", "forward_ms": fwd_ms,
+                   "backward_ms": bwd_ms, "max_steps": 1024},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel_ms": kernel_ms, "alg_flops_per_launch": f_launch},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    del grad
+    net.close()
     return 0
 
 

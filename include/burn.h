@@ -243,13 +243,14 @@ size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells
  *   status      DEVICE [n_cells]     BN_CELL_* (required: the backward call
  *                                    reads it)
  *   counters    DEVICE [BN_N_COUNTERS][n_cells] or NULL (recording run)
+ *   replay_iters DEVICE [n_cells] or NULL  Newton iterations of the replay
  * A cell that fails keeps the recording run's last accepted state. */
 int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const double *state0,
                                const double *rho, const double *T0, double dt, double rtol,
                                double atol, const double *log_mult, int32_t max_steps,
                                double *state_out, double *T_out, double *E_out,
-                               int32_t *status, int32_t *counters, void *workspace,
-                               size_t workspace_bytes, void *stream);
+                               int32_t *status, int32_t *counters, int32_t *replay_iters,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* Backward: per-cell vector-Jacobian product.
  *   gY    DEVICE [N][n_cells]   cotangent of the end abundances
@@ -269,8 +270,9 @@ int burn_batch_adjoint(const bn_network *net, int64_t n_cells, const double *sta
                        const double *rho, const double *T0, double dt, double rtol, double atol,
                        const double *log_mult, int32_t max_steps, const double *gY,
                        const double *gE, double *state_out, double *T_out, double *E_out,
-                       double *grad, int32_t *status, int32_t *counters, void *workspace,
-                       size_t workspace_bytes, void *stream);
+                       double *grad, int32_t *status, int32_t *counters,
+                       int32_t *replay_iters, void *workspace, size_t workspace_bytes,
+                       void *stream);
 
 /* Thread-local description of the last failed call on this thread ("" if
  * none); valid until the next call from the same thread. */

@@ -95,8 +95,8 @@ def lib() -> C.CDLL:
     L.burn_batch_adjoint_workspace_bytes.argtypes = [vp, C.c_int64, C.c_int32]
     L.burn_batch_adjoint_workspace_bytes.restype = C.c_size_t
     L.burn_batch_adjoint_forward.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
-                                             C.c_double, dp, C.c_int32, dp, dp, dp, ip, ip, vp,
-                                             C.c_size_t, vp]
+                                             C.c_double, dp, C.c_int32, dp, dp, dp, ip, ip, ip,
+                                             vp, C.c_size_t, vp]
     L.burn_batch_adjoint_forward.restype = C.c_int
     L.burn_batch_adjoint_backward.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
                                               C.c_double, dp, C.c_int32, dp, dp, dp, ip, vp,
@@ -104,7 +104,7 @@ def lib() -> C.CDLL:
     L.burn_batch_adjoint_backward.restype = C.c_int
     L.burn_batch_adjoint.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
                                      C.c_double, dp, C.c_int32, dp, dp, dp, dp, dp, dp, ip, ip,
-                                     vp, C.c_size_t, vp]
+                                     ip, vp, C.c_size_t, vp]
     L.burn_batch_adjoint.restype = C.c_int
     L.bn_last_error.restype = C.c_char_p
     L.bn_version.restype = C.c_char_p

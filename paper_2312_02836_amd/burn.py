@@ -254,6 +254,7 @@ class AdjointRun:
         self.E = torch.empty_like(self.T0)
         self.status = torch.empty(self.C, dtype=torch.int32, device=device)
         self.counters = torch.empty((8, self.C), dtype=torch.int32, device=device)
+        self.replay_iters = torch.empty(self.C, dtype=torch.int32, device=device)
         self.device = device
 
     def _stream(self):
@@ -263,8 +264,8 @@ class AdjointRun:
         rc = _lib.lib().burn_batch_adjoint_forward(
             self.net.handle, self.C, _ptr(self.Y0), _ptr(self.rho), _ptr(self.T0), self.dt,
             self.rtol, self.atol, _ptr(self.lm), self.max_steps, _ptr(self.Y), _ptr(self.T),
-            _ptr(self.E), _ptr(self.status), _ptr(self.counters), _ptr(self.ws), self.ws.numel(),
-            self._stream())
+            _ptr(self.E), _ptr(self.status), _ptr(self.counters), _ptr(self.replay_iters),
+            _ptr(self.ws), self.ws.numel(), self._stream())
         _lib.check(rc, "burn_batch_adjoint_forward")
         return self.Y, self.T, self.E, self.status
 

@@ -164,7 +164,10 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
     if constexpr (BACKWARD) {
       for (int r = lane; r < R; r += 64) a.grad[(int64_t)r * C + cell] = 0.0;
     } else {
-      if (lane == 0) a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
+      if (lane == 0) {
+        a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
+        if (a.iters) a.iters[cell] = 0;
+      }
     }
     return;
   }
@@ -342,6 +345,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
 
   // the replay of one accepted step; returns the corrected state in y_new
   // (this lane's component); 0 on a non-finite or singular corrector
+  int n_it = 0;  // Newton iterations of the replay
   auto replay_step = [&](int m, double &y_new) -> int {
     const int k = so[m];
     const double hstep = sh[m], ratio = sr[m];
@@ -363,6 +367,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
     double d = 0.0, y = ypred;
     int ok = 1;
     for (int it = 0; it < ADJ_MAXIT; ++it) {
+      ++n_it;
       if (own) ybuf[lane] = y;
       double F;
       ok = eval_f_m(c, true, true, F);
@@ -418,6 +423,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
       }
       ok = replay_step(m, y_new);
     }
+    if (lane == 0 && a.iters) a.iters[cell] = n_it;
     if (!ok) {
       if (lane == 0) a.status[cell] = ST_NONFINITE;
       return;

@@ -704,8 +704,8 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
                                const double *rho, const double *T0, double dt, double rtol,
                                double atol, const double *log_mult, int32_t max_steps,
                                double *state_out, double *T_out, double *E_out,
-                               int32_t *status, int32_t *counters, void *workspace,
-                               size_t workspace_bytes, void *stream) {
+                               int32_t *status, int32_t *counters, int32_t *replay_iters,
+                               void *workspace, size_t workspace_bytes, void *stream) {
   g_err.clear();
   int dev = -1;
   if (int rc = adj_check(net, n_cells, dt, rtol, atol, max_steps, workspace, workspace_bytes,
@@ -751,6 +751,7 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
   a.Yout = state_out;
   a.Tout = T_out;
   a.Eout = E_out;
+  a.iters = replay_iters;
   e = bn::launch_adjoint(a, false, adj_waves(net), st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("replay launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;
@@ -784,11 +785,12 @@ int burn_batch_adjoint(const bn_network *net, int64_t n_cells, const double *sta
                        const double *rho, const double *T0, double dt, double rtol, double atol,
                        const double *log_mult, int32_t max_steps, const double *gY,
                        const double *gE, double *state_out, double *T_out, double *E_out,
-                       double *grad, int32_t *status, int32_t *counters, void *workspace,
-                       size_t workspace_bytes, void *stream) {
+                       double *grad, int32_t *status, int32_t *counters,
+                       int32_t *replay_iters, void *workspace, size_t workspace_bytes,
+                       void *stream) {
   int rc = burn_batch_adjoint_forward(net, n_cells, state0, rho, T0, dt, rtol, atol, log_mult,
                                       max_steps, state_out, T_out, E_out, status, counters,
-                                      workspace, workspace_bytes, stream);
+                                      replay_iters, workspace, workspace_bytes, stream);
   if (rc != BN_SUCCESS) return rc;
   return burn_batch_adjoint_backward(net, n_cells, state0, rho, T0, dt, rtol, atol, log_mult,
                                      max_steps, gY, gE, grad, status, workspace, workspace_bytes,
