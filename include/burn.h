@@ -130,6 +130,20 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
                   double *T, double dt, double rtol, double atol, const double *log_mult,
                   int32_t *status, int32_t *counters, const bn_burn_opts *opts, void *stream);
 
+/* burn_batch_ex with a constant per-cell source added to the right-hand
+ * side, dy/dt = f(y) + A_adv: the advective forcing a simplified-SDC coupling
+ * hands to each zone's reaction integration (Sec. 2 of the paper: the
+ * network couples to the hydrodynamics through such integration schemes).
+ *   source  DEVICE [N+1][n_cells]  constant rates for the abundances (rows
+ *                                  0..N-1) and the temperature (row N)
+ * The source does not enter the Jacobian.  A non-finite source entry makes
+ * the cell BN_CELL_BAD_INPUT.  opts as for burn_batch_ex (its lanes_per_cell
+ * must select one of 4, 16, 32 or 64 lanes, or be 0). */
+int burn_batch_sdc(const bn_network *net, int64_t n_cells, double *state, const double *rho,
+                   double *T, double dt, double rtol, double atol, const double *log_mult,
+                   const double *source, int32_t *status, int32_t *counters,
+                   const bn_burn_opts *opts, void *stream);
+
 /* ---- Persistent multi-network burn ------------------------------------ */
 
 /* One network's batch of cells inside a multi-network launch.  The arrays

@@ -345,20 +345,35 @@ typedef struct {
 } orc_schedule;
 
 static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const double *log_mult,
-                          const orc_opts *o, int32_t *cnt, orc_schedule *sch);
+                          const double *src, const orc_opts *o, int32_t *cnt,
+                          orc_schedule *sch);
 
 /* Integrate one cell from t = 0 to t_end.  y_io holds (Y, T) on entry and
  * the last accepted state on exit.  cnt receives the eight counters.  Returns
  * the status code. */
 int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *log_mult,
                   const orc_opts *o, int32_t *cnt) {
-  return burn_cell_impl(net, rho, y_io, log_mult, o, cnt, NULL);
+  return burn_cell_impl(net, rho, y_io, log_mult, NULL, o, cnt, NULL);
+}
+
+/* Right-hand side plus a constant per-cell source term (src NULL: none).
+ * The source is the advective forcing of the simplified-SDC coupling of
+ * reactions and hydrodynamics that the network code supports (paper, Sec. 2):
+ * over a hydro step the zone's reactions see the advective change of every
+ * component as a constant rate, dy/dt = f(y) + A_adv. */
+static void rhs_src(const orc_net *net, double rho, const double *y, const double *log_mult,
+                    const double *src, double *f) {
+  orc_rhs(net, rho, y, log_mult, f);
+  if (src)
+    for (int i = 0; i <= net->n_species; i++) f[i] = f[i] + src[i];
 }
 
 /* The integrator; when sch is not NULL the schedule is recorded (up to
- * sch->cap steps, which must be >= o->max_steps). */
+ * sch->cap steps, which must be >= o->max_steps).  src: constant source
+ * [n] or NULL. */
 static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const double *log_mult,
-                          const orc_opts *o, int32_t *cnt, orc_schedule *sch) {
+                          const double *src, const orc_opts *o, int32_t *cnt,
+                          orc_schedule *sch) {
   const int N = net->n_species, n = N + 1;
   const double rtol = o->rtol, atol = o->atol, t_end = o->t_end;
   double D[(K_MAX + 3) * ORC_NMAX];
@@ -388,7 +403,7 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
     jac_current = 1;
   } else {
     /* Initial step (Hairer, Norsett & Wanner, vol. I, Sec. II.4, order 1). */
-    orc_rhs(net, rho, y0, log_mult, f0);
+    rhs_src(net, rho, y0, log_mult, src, f0);
     cnt[C_RHS]++;
     if (!all_finite(n, f0)) return ORC_NONFINITE;
     for (int i = 0; i < n; i++) s[i] = atol + rtol * fabs(y0[i]);
@@ -396,7 +411,7 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
     double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
     if (h0 > t_end) h0 = t_end;
     for (int i = 0; i < n; i++) tmp[i] = y0[i] + h0 * f0[i];
-    orc_rhs(net, rho, tmp, log_mult, f1);
+    rhs_src(net, rho, tmp, log_mult, src, f1);
     cnt[C_RHS]++;
     for (int i = 0; i < n; i++) tmp[i] = f1[i] - f0[i];
     double d2 = wrms(n, tmp, s) / h0;
@@ -480,7 +495,7 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
           double dprev = 0.0;
           for (int i = 0; i < n; i++) { d[i] = 0.0; y[i] = ypred[i]; }
           for (int it = 0; it < maxit; it++) {
-            orc_rhs(net, rho, y, log_mult, F);
+            rhs_src(net, rho, y, log_mult, src, F);
             cnt[C_RHS]++;
             if (!all_finite(n, F)) break;
             for (int i = 0; i < n; i++) dy[i] = cc * F[i] - psi[i] - d[i];
@@ -776,7 +791,7 @@ int orc_sens_batch(const orc_net *net, int64_t n_cells, double *Y, const double 
     for (int i = 0; i < N; i++) y[i] = Y[(int64_t)i * n_cells + c];
     y[N] = T[c];
     memcpy(y0, y, sizeof(double) * n);
-    int st = burn_cell_impl(net, rho[c], y, log_mult, o, cnt, &sch);
+    int st = burn_cell_impl(net, rho[c], y, log_mult, NULL, o, cnt, &sch);
     double *Sc = S ? S + (size_t)c * n * Rn : NULL;
     int unc = 0;
     if (st == ORC_OK) {
@@ -823,6 +838,37 @@ int orc_burn_batch(const orc_net *net, int64_t n_cells, double *Y, const double 
     for (int i = 0; i < N; i++) y[i] = Y[(int64_t)i * n_cells + c];
     y[N] = T[c];
     int st = orc_burn_cell(net, rho[c], y, log_mult, o, cnt);
+    for (int i = 0; i < N; i++) Y[(int64_t)i * n_cells + c] = y[i];
+    T[c] = y[N];
+    if (status) status[c] = st;
+    if (counters)
+      for (int j = 0; j < C_COUNT; j++) counters[(int64_t)j * n_cells + c] = cnt[j];
+  }
+  return 0;
+}
+
+/* orc_burn_batch with a constant per-cell source src [n][C] (rows: species,
+ * then temperature). */
+int orc_burn_batch_src(const orc_net *net, int64_t n_cells, double *Y, const double *rho,
+                       double *T, const double *log_mult, const double *src, const orc_opts *o,
+                       int32_t *status, int32_t *counters, int n_threads) {
+  int N = net->n_species, n = N + 1;
+  if (N < 1 || n > ORC_NMAX || net->n_reactions < 1 || net->n_reactions > ORC_RMAX ||
+      n_cells < 0 || !src)
+    return -1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+  (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t c = 0; c < n_cells; c++) {
+    double y[ORC_NMAX], sc[ORC_NMAX];
+    int32_t cnt[C_COUNT];
+    for (int i = 0; i < N; i++) y[i] = Y[(int64_t)i * n_cells + c];
+    y[N] = T[c];
+    for (int i = 0; i < n; i++) sc[i] = src[(int64_t)i * n_cells + c];
+    int st = burn_cell_impl(net, rho[c], y, log_mult, sc, o, cnt, NULL);
     for (int i = 0; i < N; i++) Y[(int64_t)i * n_cells + c] = y[i];
     T[c] = y[N];
     if (status) status[c] = st;

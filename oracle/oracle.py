@@ -73,6 +73,10 @@ def lib():
                                      C.POINTER(_Opts), C.POINTER(C.c_int32),
                                      C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32), C.c_int]
         L.orc_sens_batch.restype = C.c_int
+        L.orc_burn_batch_src.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, dp,
+                                         C.POINTER(_Opts), C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), C.c_int]
+        L.orc_burn_batch_src.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -193,8 +197,9 @@ def burn_fixed(net: OracleNet, rho: float, D_init, k: int, h: float, n_steps: in
 
 
 def burn(net: OracleNet, cells, t_end: float, rtol: float = 1e-6, atol: float = 1e-10,
-         log_mult=None, max_steps: int = 100000, n_threads: int = 0):
-    """Batch burn on the host.  cells: synth.Cells.  Returns
+         log_mult=None, max_steps: int = 100000, n_threads: int = 0, source=None):
+    """Batch burn on the host.  cells: synth.Cells; source: optional constant
+    per-cell source [n, C] added to the right-hand side.  Returns
     (Y[N,C], T[C], status[C], counters[8,C])."""
     Y = np.array(cells.Y, dtype=np.float64, order="C", copy=True)
     T = np.array(cells.T, dtype=np.float64, copy=True)
@@ -204,9 +209,16 @@ def burn(net: OracleNet, cells, t_end: float, rtol: float = 1e-6, atol: float = 
     cnt = np.zeros((8, C_), dtype=np.int32)
     lm = _lm(net, log_mult)
     o = _opts(t_end, rtol, atol, max_steps)
-    rc = lib().orc_burn_batch(C.byref(net.c), C_, _dp(Y), _dp(rho), _dp(T), _dp(lm), C.byref(o),
-                              st.ctypes.data_as(C.POINTER(C.c_int32)),
-                              cnt.ctypes.data_as(C.POINTER(C.c_int32)), int(n_threads))
+    if source is not None:
+        src = np.ascontiguousarray(source, dtype=np.float64)
+        assert src.shape == (net.n, C_)
+        rc = lib().orc_burn_batch_src(C.byref(net.c), C_, _dp(Y), _dp(rho), _dp(T), _dp(lm),
+                                      _dp(src), C.byref(o), st.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      cnt.ctypes.data_as(C.POINTER(C.c_int32)), int(n_threads))
+    else:
+        rc = lib().orc_burn_batch(C.byref(net.c), C_, _dp(Y), _dp(rho), _dp(T), _dp(lm),
+                                  C.byref(o), st.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  cnt.ctypes.data_as(C.POINTER(C.c_int32)), int(n_threads))
     if rc != 0:
         raise ValueError("oracle rejected the network size")
     return Y, T, st, cnt

@@ -24,7 +24,8 @@ EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "burn_batch_multi_workspace_bytes", "burn_batch_multi", "bn_network_autotune",
            "bn_network_set_launch", "bn_network_get_launch",
            "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
-           "burn_batch_adjoint_backward", "burn_batch_adjoint", "bn_last_error", "bn_version"]
+           "burn_batch_adjoint_backward", "burn_batch_adjoint", "burn_batch_sdc",
+           "bn_last_error", "bn_version"]
 MAX_ITEMS = 8
 
 
@@ -106,6 +107,9 @@ def lib() -> C.CDLL:
                                      C.c_double, dp, C.c_int32, dp, dp, dp, dp, dp, dp, ip, ip,
                                      ip, vp, C.c_size_t, vp]
     L.burn_batch_adjoint.restype = C.c_int
+    L.burn_batch_sdc.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double,
+                                 dp, dp, ip, ip, C.POINTER(BurnOpts), vp]
+    L.burn_batch_sdc.restype = C.c_int
     L.bn_last_error.restype = C.c_char_p
     L.bn_version.restype = C.c_char_p
     _lib = L

@@ -79,11 +79,13 @@ def _dev_f64(t, device) -> torch.Tensor:
 def burn(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float = 1e-10,
          log_mult=None, *, max_steps: int = 0, lanes_per_cell: int = 0, block_waves: int = 0,
          inplace: bool = False, want_status: bool = True, want_counters: bool = True,
-         device: Optional[torch.device] = None
+         device: Optional[torch.device] = None, source=None
          ) -> Tuple[torch.Tensor, torch.Tensor, Optional[torch.Tensor], Optional[torch.Tensor]]:
     """Burn every cell from t = 0 to dt on the current HIP device.
 
     Y [N, C], rho [C], T [C] (float64; moved to the device if needed).
+    source [N+1, C] (optional): constant per-cell rates added to the
+    right-hand side (burn_batch_sdc).
     Returns (Y_end, T_end, status[C] int32, counters[8, C] int32).  With
     inplace=True, Y and T (already float64 contiguous device tensors) are
     overwritten and returned.
@@ -107,6 +109,15 @@ def burn(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float = 1
     cnt = torch.empty((8, C_), dtype=torch.int32, device=device) if want_counters else None
     opts = _lib.BurnOpts(int(max_steps), int(lanes_per_cell), int(block_waves), 0)
     stream = torch.cuda.current_stream(device).cuda_stream
+    if source is not None:
+        src = _dev_f64(source, device)
+        if src.shape != (net.n_species + 1, C_):
+            raise ValueError("source must be [n_species + 1, n_cells]")
+        rc = _lib.lib().burn_batch_sdc(net.handle, C_, _ptr(Yd), _ptr(rhod), _ptr(Td), float(dt),
+                                       float(rtol), float(atol), _ptr(lm), _ptr(src), _ptr(st),
+                                       _ptr(cnt), C.byref(opts), C.c_void_p(stream))
+        _lib.check(rc, "burn_batch_sdc")
+        return Yd, Td, st, cnt
     rc = _lib.lib().burn_batch_ex(net.handle, C_, _ptr(Yd), _ptr(rhod), _ptr(Td), float(dt),
                                   float(rtol), float(atol), _ptr(lm), _ptr(st), _ptr(cnt),
                                   C.byref(opts), C.c_void_p(stream))

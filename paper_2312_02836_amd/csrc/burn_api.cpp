@@ -797,4 +797,63 @@ int burn_batch_adjoint(const bn_network *net, int64_t n_cells, const double *sta
                                      stream);
 }
 
+
+int burn_batch_sdc(const bn_network *net, int64_t n_cells, double *state, const double *rho,
+                   double *T, double dt, double rtol, double atol, const double *log_mult,
+                   const double *source, int32_t *status, int32_t *counters,
+                   const bn_burn_opts *opts, void *stream) {
+  g_err.clear();
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (n_cells < 0) return fail(BN_EINVAL, "n_cells < 0");
+  if (int rc = check_tol(dt, rtol, atol)) return rc;
+  bn_burn_opts o{};
+  if (opts) o = *opts;
+  if (o.max_steps <= 0) o.max_steps = 100000;
+  if (o.block_waves < 0 || o.block_waves > 4) return fail(BN_EINVAL, "block_waves must be 0..4");
+  int L = 0, S = 0;
+  if (o.lanes_per_cell) {
+    bool found = false;
+    for (const bn::ShapeLS &sh : bn::MULTI_SHAPES)
+      if (sh.L == o.lanes_per_cell && sh.L * sh.S >= net->n) {
+        L = sh.L;
+        S = sh.S;
+        found = true;
+        break;
+      }
+    if (!found) return fail(BN_EINVAL, "lanes_per_cell must be 0, 4, 16, 32 or 64 here");
+  } else {
+    L = net->L;
+    S = net->S;
+    if (!L || multi_shape_index(L, S) < 0) default_multi_shape(net->n, &L, &S);
+  }
+  if (n_cells == 0) return BN_SUCCESS;
+  if (!state || !rho || !T || !source) return fail(BN_EINVAL, "null state, rho, T or source");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  bn::BurnArgs a{};
+  a.net = net->tables;
+  a.n_cells = n_cells;
+  a.Y = state;
+  a.rho = rho;
+  a.T = T;
+  a.log_mult = log_mult;
+  a.status = status;
+  a.counters = counters;
+  a.t_end = dt;
+  a.rtol = rtol;
+  a.atol = atol;
+  a.max_steps = o.max_steps;
+  a.src = source;
+  int bw = o.block_waves ? o.block_waves : 2;
+  while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) --bw;
+  if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
+    return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
+  const hipError_t e = bn::launch_source(a, L, S, bw, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return BN_SUCCESS;
+}
+
 }  // extern "C"

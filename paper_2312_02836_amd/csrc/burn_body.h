@@ -305,7 +305,8 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
 // loop ends when every group of the wave is idle.  With REC the accepted
 // steps' schedule (order, step size, product of the history rescale ratios
 // since the previous accepted step) is recorded for a sensitivity replay.
-template <int L, int S, bool QUEUE, bool REC = false>
+// With SRC a constant per-cell source is added to the right-hand side.
+template <int L, int S, bool QUEUE, bool REC = false, bool SRC = false>
 __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, double *wb,
                                           int64_t first_cell, unsigned long long *queue) {
   using SH = Shape<L, S>;
@@ -338,13 +339,14 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   double dinv[S];    // 1 / U_pp of those rows
   int ridx[S];       // natural index of those rows
   double yp[S], psi[S], isc[S], dd[S], yv[S], yJ[S], F[S];
+  double srcv[S];  // constant source of the own components (SRC)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     dinv[s] = 1.0;
     ridx[s] = s * L + q;
 #pragma unroll
     for (int j = 0; j < NP; ++j) LU[s][j] = 0.0;
-    yp[s] = psi[s] = isc[s] = dd[s] = yv[s] = yJ[s] = F[s] = 0.0;
+    yp[s] = psi[s] = isc[s] = dd[s] = yv[s] = yJ[s] = F[s] = srcv[s] = 0.0;
   }
   int cnt[8];
 #pragma unroll
@@ -449,7 +451,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int i = comp(s);
-      const double f = (i < N) ? facc[i] : ((i == N) ? heat * nt.inv_cv : 0.0);
+      double f = (i < N) ? facc[i] : ((i == N) ? heat * nt.inv_cv : 0.0);
+      if constexpr (SRC) f = f + srcv[s];
       F[s] = f;
       if (i < n && !isfinite(f)) bad = 1;
     }
@@ -539,6 +542,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     for (int s = 0; s < S; ++s) {
       const int i = comp(s);
       yv[s] = (i < N) ? a.Y[(int64_t)i * C + cell] : ((i == N) ? a.T[cell] : 0.0);
+      if constexpr (SRC) srcv[s] = (i < n) ? a.src[(int64_t)i * C + cell] : 0.0;
     }
     int bad = !(rho > 0.0) || !isfinite(rho);
 #pragma unroll
@@ -546,6 +550,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const int i = comp(s);
       if (i < n && !isfinite(yv[s])) bad = 1;
       if (i == N && !(yv[s] > 0.0)) bad = 1;
+      if constexpr (SRC) {
+        if (i < n && !isfinite(srcv[s])) bad = 1;
+      }
     }
     if (gor<L>(bad)) {
       status = ST_BAD_INPUT;

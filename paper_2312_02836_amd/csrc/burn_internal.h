@@ -50,6 +50,9 @@ struct BurnArgs {
   double *sched;
   int64_t sched_stride;
   int sched_cap;
+  // Constant per-cell source [n][n_cells] added to the right-hand side
+  // (simplified-SDC forcing; nullptr otherwise).
+  const double *src;
 };
 
 // Shapes (lanes per cell L, slots per lane S; the system is padded to
@@ -109,6 +112,10 @@ int adjoint_n_ckpt(int cap);
 size_t adjoint_lds_bytes(int R, int n, int waves);
 hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_t stream);
+
+// Plain launch with a constant per-cell source (a.src != nullptr); shapes
+// of the persistent subset.
+hipError_t launch_source(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 
 // Zero n counters with a kernel (no memset node, so the sequence can be
 // captured into a graph and replayed).
