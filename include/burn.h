@@ -83,6 +83,15 @@ typedef struct {
   const double *coef;       /* [R][7] a0..a6 of the rate fit */
   const double *q;          /* [R] heat released per reaction event */
   double c_v;               /* specific heat, > 0 */
+  const double *screen;     /* [R] or NULL: strengths h_r of a synthetic
+                               screening factor, the rate of reaction r being
+                               multiplied by exp(h_r G) with
+                               G = sqrt(rho (1 + sum_j A_j^2 Y_j)) T^(-3/2)
+                               (the paper's network code screens its rates,
+                               Sec. 2; this stands in for it).  A screened
+                               network burns through burn_batch / burn_batch_ex
+                               only (the persistent, source, adjoint and
+                               autotune entry points return BN_EUNSUPPORTED) */
 } bn_network_desc;
 
 /* Validate `desc` (indices in range, every reaction conserves mass number,

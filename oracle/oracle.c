@@ -54,6 +54,7 @@ typedef struct {
   const double *coef;       /* [R][7] */
   const double *q;          /* [R] */
   double c_v;
+  const double *screen;     /* [R] screening strengths h_r, or NULL */
 } orc_net;
 
 typedef struct {
@@ -120,11 +121,31 @@ static int reaction_order(const orc_net *net, int r, double *inv_fact) {
   return n;
 }
 
-/* Reaction rates R_r at state y = (Y, T). */
+/* Synthetic screening (the network code applies plasma screening to its
+ * rates, Sec. 2; no plasma data is used here): the rate of reaction r is
+ * multiplied by F_r = exp(h_r G) with
+ *   G(rho, T, Y) = sqrt(rho S) T^(-3/2),  S = 1 + sum_j A_j^2 Y_j,
+ * a weak-screening-like dependence on density, temperature and composition.
+ * Returns G and S. */
+static double screen_G(const orc_net *net, double rho, const double *y, double *S_out) {
+  int N = net->n_species;
+  double S = 1.0;
+  for (int j = 0; j < N; j++) S += (double)net->mass[j] * (double)net->mass[j] * y[j];
+  *S_out = S;
+  double T = y[N];
+  return sqrt(rho * S) / (T * sqrt(T));
+}
+
+/* Reaction rates R_r at state y = (Y, T); lam receives the (screened) rate
+ * constants. */
 static void reaction_rates(const orc_net *net, double rho, const double *y, const double *log_mult,
                            double *R, double *lam, double *dlnlam) {
   int N = net->n_species;
   orc_rates(net, y[N], log_mult, lam, dlnlam);
+  if (net->screen) {
+    double S, G = screen_G(net, rho, y, &S);
+    for (int r = 0; r < net->n_reactions; r++) lam[r] *= exp(net->screen[r] * G);
+  }
   for (int r = 0; r < net->n_reactions; r++) {
     double inv_fact;
     int nr = reaction_order(net, r, &inv_fact);
@@ -167,12 +188,16 @@ void orc_rhs(const orc_net *net, double rho, const double *y, const double *log_
 /* Analytic Jacobian J[i*n + j] = d f_i / d y_j (row-major, n = N+1).
  * dR_r/dY_j: derivative of the slot product, one term per slot holding j,
  * each term the product of the other slots (so Y_j = 0 is handled).
- * dR_r/dT = R_r * d ln lambda_r / dT. */
+ * dR_r/dT = R_r * d ln lambda_r / dT.  With screening R_r also depends on
+ * every Y_j and on T through G: dR_r/dY_j += R_r h_r dG/dY_j with
+ * dG/dY_j = G A_j^2 / (2 S), and dR_r/dT += R_r h_r dG/dT, dG/dT = -3G/(2T). */
 void orc_jac(const orc_net *net, double rho, const double *y, const double *log_mult, double *J) {
   int N = net->n_species, Rn = net->n_reactions, n = N + 1;
   double R[ORC_RMAX], lam[ORC_RMAX], dl[ORC_RMAX];
   reaction_rates(net, rho, y, log_mult, R, lam, dl);
   memset(J, 0, sizeof(double) * n * n);
+  double G = 0.0, S = 1.0;
+  if (net->screen) G = screen_G(net, rho, y, &S);
   for (int r = 0; r < Rn; r++) {
     double inv_fact;
     int nr = reaction_order(net, r, &inv_fact);
@@ -193,6 +218,18 @@ void orc_jac(const orc_net *net, double rho, const double *y, const double *log_
       J[N * n + j] += net->q[r] * prod / net->c_v;
     }
     double dRdT = R[r] * dl[r];
+    if (net->screen) {
+      double u = net->screen[r] * R[r]; /* dR_r / dG */
+      dRdT += u * (-1.5 * G / y[N]);
+      for (int j = 0; j < N; j++) {
+        double dRdY = u * G * (double)net->mass[j] * (double)net->mass[j] / (2.0 * S);
+        for (int i = 0; i < N; i++) {
+          int v = nu(net, i, r);
+          if (v) J[i * n + j] += (double)v * dRdY;
+        }
+        J[N * n + j] += net->q[r] * dRdY / net->c_v;
+      }
+    }
     for (int i = 0; i < N; i++) {
       int v = nu(net, i, r);
       if (v) J[i * n + N] += (double)v * dRdT;

@@ -37,7 +37,8 @@ class _Net(C.Structure):
     _fields_ = [("n_species", C.c_int), ("n_reactions", C.c_int),
                 ("mass", C.POINTER(C.c_int32)), ("reactants", C.POINTER(C.c_int32)),
                 ("products", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_double)),
-                ("q", C.POINTER(C.c_double)), ("c_v", C.c_double)]
+                ("q", C.POINTER(C.c_double)), ("c_v", C.c_double),
+                ("screen", C.POINTER(C.c_double))]
 
 
 class _Opts(C.Structure):
@@ -99,10 +100,12 @@ class OracleNet:
         self.products = np.ascontiguousarray(spec.products, dtype=np.int32)
         self.coef = np.ascontiguousarray(spec.coef, dtype=np.float64)
         self.q = np.ascontiguousarray(spec.q, dtype=np.float64)
+        self.screen = (None if spec.screen is None
+                       else np.ascontiguousarray(spec.screen, dtype=np.float64))
         i32 = C.POINTER(C.c_int32)
         self.c = _Net(spec.n_species, spec.n_reactions, self.mass.ctypes.data_as(i32),
                       self.reactants.ctypes.data_as(i32), self.products.ctypes.data_as(i32),
-                      _dp(self.coef), _dp(self.q), float(spec.c_v))
+                      _dp(self.coef), _dp(self.q), float(spec.c_v), _dp(self.screen))
         self.N = spec.n_species
         self.R = spec.n_reactions
         self.n = self.N + 1

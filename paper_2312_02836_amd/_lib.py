@@ -33,7 +33,8 @@ class NetworkDesc(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32),
                 ("mass", C.POINTER(C.c_int32)), ("reactants", C.POINTER(C.c_int32)),
                 ("products", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_double)),
-                ("q", C.POINTER(C.c_double)), ("c_v", C.c_double)]
+                ("q", C.POINTER(C.c_double)), ("c_v", C.c_double),
+                ("screen", C.POINTER(C.c_double))]
 
 
 class BurnOpts(C.Structure):

@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libburn.so")
 
 SOURCES = ["burn_api.cpp", "burn_multi.hip", "burn_plain_p0.hip", "burn_plain_p1.hip",
-           "burn_plain_p2.hip", "burn_adjoint.hip", "burn_sdc.hip"]
+           "burn_plain_p2.hip", "burn_adjoint.hip", "burn_sdc.hip",
+           "burn_screen.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC",

@@ -29,9 +29,14 @@ class Network:
         m, rs, ps, cf, q = self._arrays
         i32 = C.POINTER(C.c_int32)
         f64 = C.POINTER(C.c_double)
+        scr = None
+        if spec.screen is not None:
+            scr = np.ascontiguousarray(spec.screen, dtype=np.float64)
+            self._arrays.append(scr)
         desc = _lib.NetworkDesc(spec.n_species, spec.n_reactions, m.ctypes.data_as(i32),
                                 rs.ctypes.data_as(i32), ps.ctypes.data_as(i32),
-                                cf.ctypes.data_as(f64), q.ctypes.data_as(f64), spec.c_v)
+                                cf.ctypes.data_as(f64), q.ctypes.data_as(f64), spec.c_v,
+                                scr.ctypes.data_as(f64) if scr is not None else None)
         h = C.c_void_p()
         _lib.check(_lib.lib().bn_network_create(C.byref(desc), C.byref(h)), "bn_network_create")
         self.handle = h

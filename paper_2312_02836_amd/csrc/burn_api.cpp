@@ -24,6 +24,7 @@ struct bn_network {
   // launch choice (0 = default for the system size)
   int L = 0, S = 0, block_waves = 0;
   double ms_per_cell = 0.0;  // measured by the autotuner (0 = unknown)
+  bool screened = false;
 };
 
 namespace {
@@ -167,6 +168,8 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
     for (int c = 0; c < 7; ++c)
       if (!std::isfinite(d->coef[7 * r + c])) return fail(BN_EINVAL, "non-finite rate coefficient");
     if (!std::isfinite(d->q[r])) return fail(BN_EINVAL, "non-finite heat q");
+    if (d->screen && !std::isfinite(d->screen[r]))
+      return fail(BN_EINVAL, "non-finite screening strength");
   }
 
   // Host copies of the tables.
@@ -241,8 +244,11 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
     delete net;
     return fail(BN_EHIP, "hipGetDevice failed");
   }
+  std::vector<double> scr, wsq(N);
+  if (d->screen) scr.assign(d->screen, d->screen + R);
+  for (int i = 0; i < N; ++i) wsq[i] = (double)d->mass[i] * (double)d->mass[i];
   // Layout of the device block: doubles first, then ints.
-  const size_t nd = rtab.size() + q.size() + row_w.size();
+  const size_t nd = rtab.size() + q.size() + row_w.size() + scr.size() + wsq.size();
   const size_t ni = rsp.size() + row_off.size() + row_r.size() + col_off.size() + col_ent.size() +
                     rout.size();
   const size_t bytes = nd * 8 + ni * 4 + nu8.size() + 16;
@@ -262,6 +268,8 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
   const size_t o_rtab = put(rtab.data(), rtab.size() * 8);
   const size_t o_q = put(q.data(), q.size() * 8);
   const size_t o_roww = put(row_w.data(), row_w.size() * 8);
+  const size_t o_scr = put(scr.data(), scr.size() * 8);
+  const size_t o_wsq = put(wsq.data(), wsq.size() * 8);
   const size_t o_rsp = put(rsp.data(), rsp.size() * 4);
   const size_t o_rowoff = put(row_off.data(), row_off.size() * 4);
   const size_t o_rowr = put(row_r.data(), row_r.size() * 4);
@@ -292,6 +300,9 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
   t.col_ent = reinterpret_cast<const int *>(base + o_colent);
   t.nu8 = reinterpret_cast<const signed char *>(base + o_nu8);
   t.rout = reinterpret_cast<const int *>(base + o_rout);
+  t.screen = d->screen ? reinterpret_cast<const double *>(base + o_scr) : nullptr;
+  t.wsq = reinterpret_cast<const double *>(base + o_wsq);
+  net->screened = d->screen != nullptr;
   *out = net;
   return BN_SUCCESS;
 }
@@ -345,6 +356,11 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
   a.atol = atol;
   a.max_steps = o.max_steps;
 
+  if (net->screened && multi_shape_index(L, S) < 0) {
+    if (o.lanes_per_cell)
+      return fail(BN_EUNSUPPORTED, "a screened network runs with 4, 16, 32 or 64 lanes per cell");
+    default_multi_shape(net->n, &L, &S);
+  }
   int bw = o.block_waves;
   if (bw == 0) {
     bw = (!o.lanes_per_cell && net->block_waves) ? net->block_waves : 2;
@@ -352,7 +368,9 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
   }
   if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
     return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
-  const hipError_t e = bn::launch_plain(a, L, S, bw, static_cast<hipStream_t>(stream));
+  const hipError_t e = net->screened
+                           ? bn::launch_screen(a, L, S, bw, static_cast<hipStream_t>(stream))
+                           : bn::launch_plain(a, L, S, bw, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;
 }
@@ -403,6 +421,8 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
     if (!x.net) return fail(BN_EINVAL, "null network in item " + std::to_string(j));
     if (x.net->device != dev) return fail(BN_EINVAL, "network was created on another device");
     if (x.n_cells < 0) return fail(BN_EINVAL, "n_cells < 0 in item " + std::to_string(j));
+    if (x.net->screened)
+      return fail(BN_EUNSUPPORTED, "screened networks are not supported by burn_batch_multi");
     if (x.n_cells == 0) continue;
     if (!x.state || !x.rho || !x.T)
       return fail(BN_EINVAL, "null state, rho or T in item " + std::to_string(j));
@@ -517,6 +537,7 @@ int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
   if (n_cells < 1) return fail(BN_EINVAL, "autotune needs at least one cell");
   if (!state || !rho || !T) return fail(BN_EINVAL, "null state, rho or T");
   if (int rc = check_tol(dt, rtol, atol)) return rc;
+  if (net->screened) return fail(BN_EUNSUPPORTED, "screened networks are not autotuned");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
   if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
@@ -642,6 +663,7 @@ int adj_check(const bn_network *net, int64_t n_cells, double dt, double rtol, do
     return fail(BN_EINVAL, "max_steps must be 1..1000000 for sensitivity runs");
   if (net->R > BN_ADJOINT_MAX_REACTIONS)
     return fail(BN_EUNSUPPORTED, "more reactions than BN_ADJOINT_MAX_REACTIONS");
+  if (net->screened) return fail(BN_EUNSUPPORTED, "screened networks have no adjoint");
   if (n_cells == 0) return BN_SUCCESS;
   const AdjLayout l = adj_layout(net, n_cells, max_steps);
   if (!workspace || workspace_bytes < l.total)
@@ -828,6 +850,7 @@ int burn_batch_sdc(const bn_network *net, int64_t n_cells, double *state, const 
   }
   if (n_cells == 0) return BN_SUCCESS;
   if (!state || !rho || !T || !source) return fail(BN_EINVAL, "null state, rho, T or source");
+  if (net->screened) return fail(BN_EUNSUPPORTED, "screened networks are not supported here");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
   if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");

@@ -305,8 +305,11 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
 // loop ends when every group of the wave is idle.  With REC the accepted
 // steps' schedule (order, step size, product of the history rescale ratios
 // since the previous accepted step) is recorded for a sensitivity replay.
-// With SRC a constant per-cell source is added to the right-hand side.
-template <int L, int S, bool QUEUE, bool REC = false, bool SRC = false>
+// With SRC a constant per-cell source is added to the right-hand side.  With
+// SCR every rate carries the synthetic screening factor exp(h_r G),
+// G = sqrt(rho (1 + sum_j A_j^2 Y_j)) T^(-3/2), and the Jacobian its terms
+// (a rank-one composition part u_i dG/dY_j and dG/dT in the T column).
+template <int L, int S, bool QUEUE, bool REC = false, bool SRC = false, bool SCR = false>
 __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, double *wb,
                                           int64_t first_cell, unsigned long long *queue) {
   using SH = Shape<L, S>;
@@ -340,6 +343,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   int ridx[S];       // natural index of those rows
   double yp[S], psi[S], isc[S], dd[S], yv[S], yJ[S], F[S];
   double srcv[S];  // constant source of the own components (SRC)
+  double wsqv[S];  // A_i^2 of the own species components (SCR)
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     dinv[s] = 1.0;
@@ -347,6 +351,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 #pragma unroll
     for (int j = 0; j < NP; ++j) LU[s][j] = 0.0;
     yp[s] = psi[s] = isc[s] = dd[s] = yv[s] = yJ[s] = F[s] = srcv[s] = 0.0;
+    wsqv[s] = 0.0;
+    if constexpr (SCR) {
+      if (s * L + q < nt.N) wsqv[s] = nt.wsq[s * L + q];
+    }
   }
   int cnt[8];
 #pragma unroll
@@ -419,11 +427,19 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     const double t53 = T * t13 * t13;
     const double lnT = log(T);
     const double tinv = 1.0 / T;
+    double G = 0.0;
+    if constexpr (SCR) {
+      double part = 0.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) part += wsqv[s] * yv[s];
+      G = sqrt(rho * (1.0 + gsum<L>(part))) / (T * sqrt(T));
+    }
     double heat = 0.0;
     auto one = [&](int r) __attribute__((always_inline)) {
       const double *c = s_rtab + 8 * (size_t)r;
-      const double expo =
+      double expo =
           c[0] + c[1] * tinv + c[2] * tm13 + c[3] * t13 + c[4] * T + c[5] * t53 + c[6] * lnT;
+      if constexpr (SCR) expo += nt.screen[r] * G;
       const int *sp = s_rsp + 4 * r;
       double v = exp(expo) * s_emult[r] * c[7];
       for (int i = 1; i < sp[3]; ++i) v *= rho;
@@ -688,7 +704,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const double fcc = fsel >= 0 ? fsc[4 * fj + 0] : 0.0;
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
       const bool frow = fi < MROWS;
+      double *uacc = fM + (size_t)MROWS * MS;  // screening: sum_r W_ir h_r R_r
       if (frow) {
+        if constexpr (SCR) uacc[fi] = 0.0;
         double *mr = fM + fi * MS;
         if constexpr (SH::COMPACT) {
           for (int j = 0; j < MROWS; ++j) mr[j] = (fi == j) ? 1.0 : 0.0;
@@ -702,6 +720,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       // W(i, r) dR_r/dy_j (W = nu for a species row, q/c_v for the temperature
       // row) is added, times -c, into the Newton matrix I - cJ.
       int jbad = 0;
+      double fG = 0.0, fS = 1.0;
       if (fsel >= 0) {
         const double T = fy[N];
         const double t13 = cbrt(T);
@@ -709,13 +728,23 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         const double t53 = T * t13 * t13;
         const double lnT = log(T);
         const double tinv = 1.0 / T;
+        if constexpr (SCR) {
+          for (int j = 0; j < N; ++j) fS += nt.wsq[j] * fy[j];
+          fG = sqrt(frho * fS) / (T * sqrt(T));
+        }
         for (int r = fi; r < R; r += FL) {
           const double *c = s_rtab + 8 * (size_t)r;
-          const double expo =
+          double expo =
               c[0] + c[1] * tinv + c[2] * tm13 + c[3] * t13 + c[4] * T + c[5] * t53 + c[6] * lnT;
-          const double dl = -c[1] * tinv * tinv - (1.0 / 3.0) * c[2] * tm13 * tinv +
-                            (1.0 / 3.0) * c[3] * t13 * tinv + c[4] +
-                            (5.0 / 3.0) * c[5] * t13 * t13 + c[6] * tinv;
+          double dl = -c[1] * tinv * tinv - (1.0 / 3.0) * c[2] * tm13 * tinv +
+                      (1.0 / 3.0) * c[3] * t13 * tinv + c[4] +
+                      (5.0 / 3.0) * c[5] * t13 * t13 + c[6] * tinv;
+          double hr = 0.0;
+          if constexpr (SCR) {
+            hr = nt.screen[r];
+            expo += hr * fG;
+            dl += hr * (-1.5 * fG * tinv);  // d(h G)/dT
+          }
           const int *sp = s_rsp + 4 * r;
           double pre = exp(expo) * s_emult[r] * c[7];
           for (int i = 1; i < sp[3]; ++i) pre *= frho;
@@ -756,6 +785,28 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
           }
+          if constexpr (SCR) {
+            // dR_r/dG = h_r R_r, gathered per row for the rank-one term
+            const double u = hr * full;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+              if (e < r0.x)
+                __hip_atomic_fetch_add(&uacc[ent[e] >> 8], (double)(signed char)(ent[e] & 0xff) * u,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+            __hip_atomic_fetch_add(&uacc[N], qc * u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+          }
+        }
+      }
+      if constexpr (SCR) {
+        // rank-one composition term: -c u_i dG/dY_j, dG/dY_j = G A_j^2 / (2 S)
+        wave_lds_sync();
+        if (fsel >= 0 && fi < n) {
+          const double ui = -fcc * uacc[fi] * fG / (2.0 * fS);
+          double *mr = fM + fi * MS;
+          for (int j = 0; j < N; ++j) mr[j] += ui * nt.wsq[j];
+          if (!isfinite(ui)) jbad = 1;
         }
       }
       jbad = gor<FL>(jbad);

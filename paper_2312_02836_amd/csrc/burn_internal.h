@@ -29,6 +29,8 @@ struct NetTables {
   const int *col_ent;  // [nsl] (r << 2) | slot, ascending in r then slot
   const signed char *nu8;  // [N][R] dense nu_ir
   const int *rout;     // [R][8]: count, then (species << 8) | (nu_ir & 0xff) for nu_ir != 0
+  const double *screen;  // [R] screening strengths h_r, or nullptr
+  const double *wsq;     // [N] A_j^2 (screening)
 };
 
 struct BurnArgs {
@@ -116,6 +118,10 @@ hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_
 // Plain launch with a constant per-cell source (a.src != nullptr); shapes
 // of the persistent subset.
 hipError_t launch_source(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
+
+// Plain launch of a screened network (a.net.screen != nullptr); shapes of
+// the persistent subset.
+hipError_t launch_screen(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 
 // Zero n counters with a kernel (no memset node, so the sequence can be
 // captured into a graph and replayed).

@@ -43,6 +43,8 @@ class NetworkSpec:
     coef       float64[R, 7]  ReacLib-form coefficients a0..a6
     q          float64[R]     heat released per reaction event
     c_v        float          constant specific heat (> 0)
+    screen     float64[R] or None  strengths h_r of the synthetic screening
+                              factor exp(h_r G(rho, T, Y)) (None: no screening)
     """
 
     name: str
@@ -52,6 +54,7 @@ class NetworkSpec:
     coef: np.ndarray
     q: np.ndarray
     c_v: float
+    screen: Optional[np.ndarray] = None
 
     @property
     def n_species(self) -> int:
@@ -73,6 +76,8 @@ class NetworkSpec:
         self.coef = np.ascontiguousarray(self.coef, dtype=np.float64).reshape(-1, N_COEF)
         self.q = np.ascontiguousarray(self.q, dtype=np.float64).reshape(-1)
         self.c_v = float(self.c_v)
+        if self.screen is not None:
+            self.screen = np.ascontiguousarray(self.screen, dtype=np.float64).reshape(-1)
 
     def validate(self) -> None:
         """Raise ValueError unless indices are in range and every reaction
@@ -90,6 +95,9 @@ class NetworkSpec:
             raise ValueError("coef must be [R,7] and q must be [R]")
         if not (self.c_v > 0 and math.isfinite(self.c_v)):
             raise ValueError("c_v must be positive and finite")
+        if self.screen is not None and (self.screen.shape != (R,)
+                                        or not np.all(np.isfinite(self.screen))):
+            raise ValueError("screen must be [R] and finite")
         for r in range(R):
             rs = [int(s) for s in self.reactants[r] if s >= 0]
             ps = [int(s) for s in self.products[r] if s >= 0]
@@ -102,14 +110,15 @@ class NetworkSpec:
         return json.dumps({
             "name": self.name, "mass": self.mass.tolist(),
             "reactants": self.reactants.tolist(), "products": self.products.tolist(),
-            "coef": self.coef.tolist(), "q": self.q.tolist(), "c_v": self.c_v})
+            "coef": self.coef.tolist(), "q": self.q.tolist(), "c_v": self.c_v,
+            "screen": None if self.screen is None else self.screen.tolist()})
 
     @staticmethod
     def from_json(text: str) -> "NetworkSpec":
         d = json.loads(text)
         return NetworkSpec(d["name"], np.array(d["mass"]), np.array(d["reactants"]),
                            np.array(d["products"]), np.array(d["coef"]), np.array(d["q"]),
-                           d["c_v"])
+                           d["c_v"], None if d.get("screen") is None else np.array(d["screen"]))
 
     def describe(self) -> List[str]:
         """Human-readable reaction list, e.g. ``s0 + s1 -> s2``."""
@@ -461,6 +470,20 @@ def config(i: int, n_cells: Optional[int] = None) -> BurnConfig:
         cells = draw_cells(s + 1, net, C, T_range=(1.0, 5.0), rho_range=(1.0, 1e3))
         return BurnConfig("adjoint21x60-65536", [net], [cells], t_end=1e-2)
     raise KeyError(i)
+
+
+def screened(net: NetworkSpec, strength: float = 0.005) -> NetworkSpec:
+    """The same network with synthetic screening: h_r = strength times
+    (number of reactants - 1), so one-body reactions are unscreened and
+    three-body ones twice as strongly as two-body ones.  With rho <= 1e3 and
+    T >= 1, G <= ~300 on the workloads, so h_r G stays O(1).  (A stand-in for
+    real screening; no plasma data is used.)"""
+    h = np.zeros(net.n_reactions)
+    for r in range(net.n_reactions):
+        k = int((net.reactants[r] >= 0).sum())
+        h[r] = strength * (k - 1)
+    return NetworkSpec(net.name + "-screened", net.mass.copy(), net.reactants.copy(),
+                       net.products.copy(), net.coef.copy(), net.q.copy(), net.c_v, h)
 
 
 # ---------------------------------------------------------------------------
