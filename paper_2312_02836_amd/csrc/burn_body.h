@@ -101,6 +101,11 @@ __device__ __forceinline__ double gbcast(double v) {
     return v;
   } else if constexpr (G == 4) {
     return dpp_f64<SRC | (SRC << 2) | (SRC << 4) | (SRC << 6)>(v);
+  } else if constexpr (G == 16) {
+    return dpp_f64<0x150 + SRC>(v);  // row_newbcast: lane SRC of each row
+  } else if constexpr (G == 8) {
+    const double a = dpp_f64<0x150 + SRC>(v), b = dpp_f64<0x150 + 8 + SRC>(v);
+    return (threadIdx.x & 8) ? b : a;
   } else if constexpr (G == 64) {
     return readlane_f64(v, SRC);
   } else if constexpr (G == 32) {
@@ -113,40 +118,59 @@ __device__ __forceinline__ double gbcast(double v) {
 
 // Reduction levels of an aligned group of G lanes.  Each level pairs every
 // lane with another (an involution), and after all levels every lane has
-// combined all G values: groups of 16/8 use the DPP row mirror / half-row
-// mirror, then the quad permutes [2,3,0,1] and [1,0,3,2]; 32/64 use
-// ds_bpermute butterflies.
+// combined all G values (see xch).
 template <int G>
 constexpr int n_levels() {
   return G >= 64 ? 6 : G >= 32 ? 5 : G >= 16 ? 4 : G >= 8 ? 3 : G >= 4 ? 2 : G >= 2 ? 1 : 0;
 }
 
+// Exchange with the lane 16 (32) apart: gfx950's permlane16 (permlane32)
+// swap of a register with itself leaves the even and odd rows (the two
+// halves) in its two results; each lane takes its partner's.
+__device__ __forceinline__ int xor16_i32(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (threadIdx.x & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ int xor32_i32(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (threadIdx.x & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ double xor16_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = xor16_i32((int)(b & 0xffffffffLL)), hi = xor16_i32((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+__device__ __forceinline__ double xor32_f64(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = xor32_i32((int)(b & 0xffffffffLL)), hi = xor32_i32((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Level LV of a G-lane reduction: from the last level backwards, xor 1 and
+// xor 2 (DPP quad permutes), the half-row and row mirrors (DPP), then xor 16
+// and xor 32 (permlane swaps).  All stay in VALU.
 template <int G, int LV>
 __device__ __forceinline__ double xch(double v) {
   constexpr int NL = n_levels<G>();
-  constexpr int FROM_END = NL - 1 - LV;  // 0 = xor 1, 1 = xor 2, 2 = half mirror, 3 = mirror
-  if constexpr (G <= 16) {
-    if constexpr (FROM_END == 0) return dpp_f64<0xB1>(v);
-    else if constexpr (FROM_END == 1) return dpp_f64<0x4E>(v);
-    else if constexpr (FROM_END == 2) return dpp_f64<0x141>(v);
-    else return dpp_f64<0x140>(v);
-  } else {
-    return __shfl_xor(v, 1 << FROM_END, G);
-  }
+  constexpr int FROM_END = NL - 1 - LV;
+  if constexpr (FROM_END == 0) return dpp_f64<0xB1>(v);
+  else if constexpr (FROM_END == 1) return dpp_f64<0x4E>(v);
+  else if constexpr (FROM_END == 2) return dpp_f64<0x141>(v);
+  else if constexpr (FROM_END == 3) return dpp_f64<0x140>(v);
+  else if constexpr (FROM_END == 4) return xor16_f64(v);
+  else return xor32_f64(v);
 }
 
 template <int G, int LV>
 __device__ __forceinline__ int xch_i(int v) {
   constexpr int NL = n_levels<G>();
   constexpr int FROM_END = NL - 1 - LV;
-  if constexpr (G <= 16) {
-    if constexpr (FROM_END == 0) return dpp_i32<0xB1>(v);
-    else if constexpr (FROM_END == 1) return dpp_i32<0x4E>(v);
-    else if constexpr (FROM_END == 2) return dpp_i32<0x141>(v);
-    else return dpp_i32<0x140>(v);
-  } else {
-    return __shfl_xor(v, 1 << FROM_END, G);
-  }
+  if constexpr (FROM_END == 0) return dpp_i32<0xB1>(v);
+  else if constexpr (FROM_END == 1) return dpp_i32<0x4E>(v);
+  else if constexpr (FROM_END == 2) return dpp_i32<0x141>(v);
+  else if constexpr (FROM_END == 3) return dpp_i32<0x140>(v);
+  else if constexpr (FROM_END == 4) return xor16_i32(v);
+  else return xor32_i32(v);
 }
 
 // All-reduce sum; every lane ends with the bitwise same value because each
