@@ -2,12 +2,12 @@
 
 Workloads (--workload):
   synth13  (default) burn of the synthetic 13-species / 30-reaction
-           network, 65,536 cells, dt = 1e-2, in one persistent launch (the
-           fastest schedule for it), with the plain kernel (static map of
-           cells to lane groups, same shape) timed beside it;
+           network, 65,536 cells, dt = 1e-2, one plain kernel launch (static
+           map of cells to lane groups, the fastest schedule for one small
+           network), with the persistent launch timed beside it;
   mixed4   four networks (13/30, 21/60, 35/100, 50/150), 65,536 cells each,
            in ONE persistent launch with a device work queue; the plain
-           kernel (one launch per network, same shapes) is timed beside it;
+           kernel (one launch per network) is timed beside it;
   synth50  the 50-species / 150-reaction network, 1,048,576 cells, one
            persistent launch, with the plain launch timed beside it;
   adjoint21  sensitivities of the 21-species / 60-reaction network, 65,536
@@ -35,12 +35,13 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_body.h",
+                  "paper_2312_02836_amd/csrc/burn_plain.h",
                   "paper_2312_02836_amd/csrc/burn_multi.hip",
                   "paper_2312_02836_amd/csrc/burn_internal.h"]
-TRAFFIC_FILE = "profiles/burn_multi_kernel__synth13_30__65536cells__hbm_traffic.txt"
+TRAFFIC_FILE = "profiles/burn_plain_kernel__synth13_30__65536cells__hbm_traffic.txt"
 
 WORKLOADS = {
-    "synth13": dict(config=2, cells=65536, mode="persistent",
+    "synth13": dict(config=2, cells=65536, mode="plain",
                     text="burn of one synthetic 13-species/30-reaction network, {cells} cells, "
                          "dt=1e-2, rtol 1e-6, atol 1e-10"),
     "mixed4": dict(config=4, cells=65536, mode="persistent",
@@ -95,8 +96,8 @@ def main() -> int:
     ap.add_argument("--block-waves", type=int, default=0)
     ap.add_argument("--mode", choices=["plain", "persistent"], default=None,
                     help="override the workload's launch mode")
-    ap.add_argument("--no-plain", action="store_true",
-                    help="persistent workloads: skip timing the plain launches beside them")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="time only the workload's schedule (not the other one beside it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -157,7 +158,7 @@ def main() -> int:
         _lib.check(rc, "burn_batch_ex")
 
     multi = None
-    if wl["mode"] == "persistent":
+    if wl["mode"] == "persistent" or not args.no_compare:
         multi = B.MultiBurn([(b["net"], b["Yw"], b["rho"], b["Tw"]) for b in batches], cfg.t_end,
                             cfg.rtol, cfg.atol, block_waves=args.block_waves)
         for b, o in zip(batches, multi.outputs):  # MultiBurn owns its status/counter tensors
@@ -203,14 +204,16 @@ def main() -> int:
               f"kernel {np.mean(kms):.3f} ms (min {min(kms):.3f})", file=sys.stderr, flush=True)
         return 1000.0 * wall / args.steps, float(np.mean(kms))
 
-    plain_ms = plain_kernel_ms = None
+    other = None  # (schedule, ms/step, kernel ms) of the schedule timed beside
     if wl["mode"] == "plain":
+        if not args.no_compare:
+            other = ("persistent",) + timed(step_persistent, "persistent (one launch)")
         ms_per_step, kernel_ms = timed(step_plain, "plain")
         outs = [(b["st"], b["cnt"]) for b in batches]
         kernel_name = "burn_plain_kernel"
     else:
-        if not args.no_plain:
-            plain_ms, plain_kernel_ms = timed(step_plain, "plain (one launch per network)")
+        if not args.no_compare:
+            other = ("plain",) + timed(step_plain, "plain (one launch per network)")
         ms_per_step, kernel_ms = timed(step_persistent, "persistent (one launch)")
         outs = [(b["st_m"], b["cnt_m"]) for b in batches]
         kernel_name = "burn_multi_kernel"
@@ -231,16 +234,20 @@ def main() -> int:
         cpu = cpu_baseline(batches, cfg, args.cpu_seconds)
 
     traffic = None
-    if (args.workload == "synth13" and wl["mode"] == "persistent"
+    if (args.workload == "synth13" and wl["mode"] == "plain"
             and (n_cells, args.lanes, args.block_waves) == (65536, 0, 0)):
         traffic = measured_traffic()
     config = {"workload": wl["text"].format(cells=n_cells), "cells_per_network": n_cells,
               "networks": [f"{b['spec'].n_species}/{b['spec'].n_reactions}" for b in batches],
               "t_end": cfg.t_end, "kernel": kernel_name,
               "launch": [list(b["net"].get_launch()) for b in batches]}
-    if plain_ms is not None:
-        config.update({"plain_ms_per_step": plain_ms, "plain_kernel_ms": plain_kernel_ms,
-                       "vs_plain": plain_kernel_ms / kernel_ms})
+    config[f"{'plain' if wl['mode'] == 'plain' else 'persistent'}_kernel_ms"] = kernel_ms
+    if other is not None:
+        config[f"{other[0]}_kernel_ms"] = other[2]
+        # the persistent launch against one plain launch per network
+        pers = kernel_ms if wl["mode"] == "persistent" else other[2]
+        plain = kernel_ms if wl["mode"] == "plain" else other[2]
+        config["persistent_vs_plain"] = plain / pers
     out = {
         "metric": "cell-burns/s (FP64, rtol 1e-6)",
         "value": value,

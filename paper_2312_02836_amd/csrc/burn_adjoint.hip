@@ -586,7 +586,7 @@ size_t adjoint_lds_bytes(int R, int n, int waves) {
 }
 
 hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
-#define BN_REC(l, s)                                                                          \
+#define BN_REC(l, s, w)                                                                          \
   if (L == l && S == s) {                                                                      \
     using SH = Shape<l, s>;                                                                    \
     const size_t lds =                                                                         \
@@ -594,14 +594,14 @@ hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipSt
     const int64_t per = (int64_t)SH::CPW * block_waves;                                        \
     const int64_t blocks = (a.n_cells + per - 1) / per;                                        \
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;                                      \
-    hipLaunchKernelGGL((burn_record_kernel<l, s, 1>), dim3((unsigned)blocks),                  \
+    hipLaunchKernelGGL((burn_record_kernel<l, s, w>), dim3((unsigned)blocks),                  \
                        dim3(64 * block_waves), lds, stream, a, block_waves);                   \
     return hipGetLastError();                                                                  \
   }
-  BN_REC(4, 4)
-  BN_REC(16, 2)
-  BN_REC(32, 1)
-  BN_REC(64, 1)
+  BN_REC(8, 1, 2)
+  BN_REC(16, 1, 2)
+  BN_REC(32, 1, 2)
+  BN_REC(64, 1, 1)
 #undef BN_REC
   return hipErrorInvalidValue;
 }

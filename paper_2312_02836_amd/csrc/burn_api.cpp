@@ -73,23 +73,47 @@ bool plain_shape(int L, int S) {
   return false;
 }
 
+// waves per SIMD a plain shape is compiled for
+int plain_waves(int L, int S) {
+  for (const bn::ShapeLS &sh : bn::PLAIN_SHAPES)
+    if (sh.L == L && sh.S == S) return sh.W;
+  return 1;
+}
+
+// index of (L, S) in MULTI_SHAPES_2 (the two-waves-per-SIMD set used by the
+// persistent kernel and the recording / source / screened kernels), or -1
 int multi_shape_index(int L, int S) {
   for (int i = 0; i < bn::N_MULTI_SHAPES; ++i)
-    if (bn::MULTI_SHAPES[i].L == L && bn::MULTI_SHAPES[i].S == S) return i;
+    if (bn::MULTI_SHAPES_2[i].L == L && bn::MULTI_SHAPES_2[i].S == S) return i;
   return -1;
 }
 
-// Default shape for a system of size n (before any tuning).
+int multi1_shape_index(int L, int S) {
+  for (int i = 0; i < bn::N_MULTI_SHAPES; ++i)
+    if (bn::MULTI_SHAPES_1[i].L == L && bn::MULTI_SHAPES_1[i].S == S) return i;
+  return -1;
+}
+
+// Default shape for a system of size n (before any tuning): the narrowest
+// group whose padded size holds the system, at two waves per SIMD.
 void default_shape(int n, int *L, int *S) {
   if (n <= 4) { *L = 4; *S = 1; }
-  else if (n <= 8) { *L = 4; *S = 2; }
-  else if (n <= 16) { *L = 4; *S = 4; }
-  else if (n <= 32) { *L = 16; *S = 2; }
+  else if (n <= 8) { *L = 8; *S = 1; }
+  else if (n <= 16) { *L = 16; *S = 1; }
+  else if (n <= 32) { *L = 32; *S = 1; }
   else { *L = 64; *S = 1; }
 }
 
-// Default for the persistent kernel (its shapes are a subset).
+// Default within MULTI_SHAPES_2.
 void default_multi_shape(int n, int *L, int *S) {
+  if (n <= 8) { *L = 8; *S = 1; }
+  else if (n <= 16) { *L = 16; *S = 1; }
+  else if (n <= 32) { *L = 32; *S = 1; }
+  else { *L = 64; *S = 1; }
+}
+
+// Default within MULTI_SHAPES_1.
+void default_multi1_shape(int n, int *L, int *S) {
   if (n <= 16) { *L = 4; *S = 4; }
   else if (n <= 32) { *L = 16; *S = 2; }
   else { *L = 64; *S = 1; }
@@ -358,12 +382,13 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
 
   if (net->screened && multi_shape_index(L, S) < 0) {
     if (o.lanes_per_cell)
-      return fail(BN_EUNSUPPORTED, "a screened network runs with 4, 16, 32 or 64 lanes per cell");
+      return fail(BN_EUNSUPPORTED, "a screened network runs with 8, 16, 32 or 64 lanes per cell");
     default_multi_shape(net->n, &L, &S);
   }
   int bw = o.block_waves;
   if (bw == 0) {
-    bw = (!o.lanes_per_cell && net->block_waves) ? net->block_waves : 2;
+    bw = (!o.lanes_per_cell && net->block_waves) ? net->block_waves
+                                                  : (plain_waves(L, S) == 2 ? 1 : 2);
     while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) bw /= 2;
   }
   if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
@@ -410,6 +435,7 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
   // validate and collect the non-empty items
   struct It {
     bn::BurnArgs a;
+    int L, S;  // the network's launch choice (0: none)
     int shape;
     double cost;
   };
@@ -426,10 +452,9 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
     if (x.n_cells == 0) continue;
     if (!x.state || !x.rho || !x.T)
       return fail(BN_EINVAL, "null state, rho or T in item " + std::to_string(j));
-    int L = x.net->L, S = x.net->S;
-    if (!L || multi_shape_index(L, S) < 0) default_multi_shape(x.net->n, &L, &S);
     It it{};
-    it.shape = multi_shape_index(L, S);
+    it.L = x.net->L;
+    it.S = x.net->S;
     bn::BurnArgs &a = it.a;
     a.net = x.net->tables;
     a.n_cells = x.n_cells;
@@ -448,10 +473,45 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
     it.cost = x.net->ms_per_cell > 0.0 ? x.net->ms_per_cell : 1e-6 * (n * n * n + 40.0 * x.net->R);
     its.push_back(it);
     total += x.n_cells;
-    tabd = std::max(tabd, bn::table_lds_bytes(x.net->R) / 8);
-    waved = std::max(waved, bn::wave_lds_bytes(L, S, x.net->n) / 8);
   }
   if (its.empty()) return BN_SUCCESS;
+  // Two waves per SIMD unless a network's launch choice is a one-wave shape,
+  // or LDS would hold fewer than 6 waves per CU at two (the largest networks).
+  auto assign = [&](int W) {
+    tabd = 0;
+    waved = 0;
+    for (It &it : its) {
+      int L = it.L, S = it.S;
+      const int n = it.a.net.n;
+      if (W == 2) {
+        if (!L || multi_shape_index(L, S) < 0) default_multi_shape(n, &L, &S);
+        it.shape = multi_shape_index(L, S);
+      } else {
+        if (!L || multi1_shape_index(L, S) < 0) default_multi1_shape(n, &L, &S);
+        it.shape = multi1_shape_index(L, S);
+      }
+      tabd = std::max(tabd, bn::table_lds_bytes(it.a.net.R) / 8);
+      waved = std::max(waved, bn::wave_lds_bytes(L, S, n) / 8);
+    }
+  };
+  auto block_waves_for = [&](int bw0) {
+    int bw = bw0;
+    while (bw > 1 && 8 * (tabd + (size_t)bw * waved) > lim.lds_block) bw /= 2;
+    return bw;
+  };
+  int W = 2;
+  for (const It &it : its)
+    if (it.L && multi_shape_index(it.L, it.S) < 0 && multi1_shape_index(it.L, it.S) >= 0) W = 1;
+  assign(W);
+  if (W == 2) {
+    const int bw = block_waves_for(o.block_waves ? o.block_waves : 4);
+    const size_t lds = 8 * (tabd + (size_t)bw * waved);
+    const size_t resident = std::min<size_t>(8 / bw, lim.lds_cu / lds) * bw;
+    if (resident < 6) {
+      W = 1;
+      assign(W);
+    }
+  }
   const size_t need = burn_batch_multi_workspace_bytes((int32_t)its.size());
   if (!workspace || workspace_bytes < need)
     return fail(BN_EINVAL, "workspace missing or smaller than burn_batch_multi_workspace_bytes");
@@ -469,15 +529,14 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
   m.queue = static_cast<unsigned long long *>(workspace);
   m.tab_doubles = tabd;
   m.wave_doubles = waved;
-  // One wave per SIMD (4 per CU).  Workgroups of block_waves waves; as many
-  // workgroups per CU as LDS allows, up to 4 waves per CU.
-  int bw = o.block_waves ? o.block_waves : 4;
-  while (bw > 1 && 8 * (tabd + (size_t)bw * waved) > lim.lds_block) bw /= 2;
+  // W waves per SIMD (4 W per CU).  Workgroups of block_waves waves; as many
+  // workgroups per CU as LDS allows, up to 4 W waves per CU.
+  const int bw = block_waves_for(o.block_waves ? o.block_waves : 4);
   const size_t lds = 8 * (tabd + (size_t)bw * waved);
   if (lds > lim.lds_block)
     return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
   m.block_waves = bw;
-  int per_cu = std::max(1, 4 / bw);
+  int per_cu = std::max(1, 4 * W / bw);
   per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, lim.lds_cu / lds));
   int64_t grid = (int64_t)lim.cus * per_cu;
   // no more workgroups than there are cells to start
@@ -488,7 +547,7 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
   hipError_t e = bn::launch_zero(m.queue, m.n_items, st);
   if (e != hipSuccess)
     return fail(BN_EHIP, std::string("counter reset launch failed: ") + hipGetErrorString(e));
-  e = bn::launch_multi(m, (int)grid, st);
+  e = bn::launch_multi(m, (int)grid, W, st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;
 }
@@ -764,7 +823,7 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
   b.sched_cap = a.sched_cap;
   DeviceLimits lim;
   if (int rc = device_limits(dev, &lim)) return rc;
-  int bw = 2;
+  int bw = plain_waves(L, S) == 2 ? 1 : 2;
   while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) --bw;
   if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
     return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
@@ -835,14 +894,14 @@ int burn_batch_sdc(const bn_network *net, int64_t n_cells, double *state, const 
   int L = 0, S = 0;
   if (o.lanes_per_cell) {
     bool found = false;
-    for (const bn::ShapeLS &sh : bn::MULTI_SHAPES)
+    for (const bn::ShapeLS &sh : bn::MULTI_SHAPES_2)
       if (sh.L == o.lanes_per_cell && sh.L * sh.S >= net->n) {
         L = sh.L;
         S = sh.S;
         found = true;
         break;
       }
-    if (!found) return fail(BN_EINVAL, "lanes_per_cell must be 0, 4, 16, 32 or 64 here");
+    if (!found) return fail(BN_EINVAL, "lanes_per_cell must be 0, 8, 16, 32 or 64 here");
   } else {
     L = net->L;
     S = net->S;
@@ -870,7 +929,7 @@ int burn_batch_sdc(const bn_network *net, int64_t n_cells, double *state, const 
   a.atol = atol;
   a.max_steps = o.max_steps;
   a.src = source;
-  int bw = o.block_waves ? o.block_waves : 2;
+  int bw = o.block_waves ? o.block_waves : (plain_waves(L, S) == 2 ? 1 : 2);
   while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) --bw;
   if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
     return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");

@@ -57,16 +57,22 @@ struct BurnArgs {
   const double *src;
 };
 
-// Shapes (lanes per cell L, slots per lane S; the system is padded to
-// NP = L*S components).  Plain kernels exist for every shape below; the
-// persistent multi-network kernel for the MULTI_SHAPES subset.
+// Shapes: lanes per cell L, slots per lane S (the system is padded to
+// NP = L*S components) and the waves per SIMD W the kernel is compiled for
+// (W = 2 for the shapes whose registers fit half the file).  Plain kernels
+// exist for every PLAIN_SHAPES entry.  The persistent kernel is built twice:
+// for W = 2 with the shapes of MULTI_SHAPES_2 and for W = 1 with those of
+// MULTI_SHAPES_1; the recording, source and screened kernels use
+// MULTI_SHAPES_2 (with (64,1) at W = 1).
 struct ShapeLS {
-  int L, S;
+  int L, S, W;
 };
-constexpr ShapeLS PLAIN_SHAPES[] = {{4, 1}, {4, 2}, {4, 4}, {8, 4}, {16, 2},
-                                    {32, 1}, {16, 4}, {32, 2}, {64, 1}};
-constexpr int N_PLAIN_SHAPES = 9;
-constexpr ShapeLS MULTI_SHAPES[] = {{4, 4}, {16, 2}, {32, 1}, {64, 1}};
+constexpr ShapeLS PLAIN_SHAPES[] = {{4, 1, 2},  {4, 2, 2},  {4, 4, 1},  {8, 1, 2},
+                                    {8, 2, 2},  {8, 4, 1},  {16, 1, 2}, {16, 2, 1},
+                                    {32, 1, 2}, {16, 4, 1}, {32, 2, 1}, {64, 1, 1}};
+constexpr int N_PLAIN_SHAPES = 12;
+constexpr ShapeLS MULTI_SHAPES_2[] = {{8, 1, 2}, {16, 1, 2}, {32, 1, 2}, {64, 1, 2}};
+constexpr ShapeLS MULTI_SHAPES_1[] = {{4, 4, 1}, {16, 2, 1}, {32, 1, 1}, {64, 1, 1}};
 constexpr int N_MULTI_SHAPES = 4;
 
 // LDS bytes of the network tables and of one wave's working area.
@@ -82,14 +88,14 @@ hipError_t launch_plain(const BurnArgs &a, int L, int S, int block_waves, hipStr
 constexpr int MAX_ITEMS = 8;
 struct MultiArgs {
   BurnArgs item[MAX_ITEMS];
-  int shape[MAX_ITEMS];           // index into MULTI_SHAPES
+  int shape[MAX_ITEMS];           // index into MULTI_SHAPES_2 or MULTI_SHAPES_1
   unsigned long long *queue;      // [n_items] counters, zeroed before the launch
   int n_items;
   int block_waves;
   size_t tab_doubles;             // LDS doubles reserved for tables (max over items)
   size_t wave_doubles;            // LDS doubles per wave area (max over items)
 };
-hipError_t launch_multi(const MultiArgs &m, int grid, hipStream_t stream);
+hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream);
 
 // Sensitivity runs (discrete adjoint with respect to the log-rate
 // multipliers).  The replay / adjoint kernels take one cell per wave.
@@ -116,11 +122,11 @@ hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipSt
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_t stream);
 
 // Plain launch with a constant per-cell source (a.src != nullptr); shapes
-// of the persistent subset.
+// of MULTI_SHAPES_2.
 hipError_t launch_source(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 
 // Plain launch of a screened network (a.net.screen != nullptr); shapes of
-// the persistent subset.
+// MULTI_SHAPES_2.
 hipError_t launch_screen(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 
 // Zero n counters with a kernel (no memset node, so the sequence can be

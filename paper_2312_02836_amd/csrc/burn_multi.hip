@@ -1,6 +1,9 @@
 // burn_multi.hip -- the persistent multi-network kernel, the counter reset
 // kernel, and the host-side shape dispatch and LDS sizing for all kernels.
 //
+// The kernel is built for two waves per SIMD (the narrow shapes, whose
+// registers fit half the file) and for one (the wide ones).
+//
 // Persistent scheduling: the grid is sized to the machine (one or a few
 // workgroups per compute unit), not to the work.  Every workgroup walks the
 // batch items in the order given (the host puts the costliest cells first);
@@ -44,11 +47,20 @@ burn_multi_kernel(MultiArgs m) {
     if (skip) continue;
     const Tabs tb = tabs_at(smem, a.net.R);
     unsigned long long *qj = m.queue + j;
-    switch (m.shape[j]) {
-      case 0: run_cells<4, 4, true>(a, tb, wb, 0, qj); break;
-      case 1: run_cells<16, 2, true>(a, tb, wb, 0, qj); break;
-      case 2: run_cells<32, 1, true>(a, tb, wb, 0, qj); break;
-      default: run_cells<64, 1, true>(a, tb, wb, 0, qj); break;
+    if constexpr (W == 2) {
+      switch (m.shape[j]) {
+        case 0: run_cells<8, 1, true>(a, tb, wb, 0, qj); break;
+        case 1: run_cells<16, 1, true>(a, tb, wb, 0, qj); break;
+        case 2: run_cells<32, 1, true>(a, tb, wb, 0, qj); break;
+        default: run_cells<64, 1, true>(a, tb, wb, 0, qj); break;
+      }
+    } else {
+      switch (m.shape[j]) {
+        case 0: run_cells<4, 4, true>(a, tb, wb, 0, qj); break;
+        case 1: run_cells<16, 2, true>(a, tb, wb, 0, qj); break;
+        case 2: run_cells<32, 1, true>(a, tb, wb, 0, qj); break;
+        default: run_cells<64, 1, true>(a, tb, wb, 0, qj); break;
+      }
     }
   }
 }
@@ -73,7 +85,10 @@ size_t wave_lds_bytes(int L, int S, int n) {
   BN_W(4, 1)
   BN_W(4, 2)
   BN_W(4, 4)
+  BN_W(8, 1)
+  BN_W(8, 2)
   BN_W(8, 4)
+  BN_W(16, 1)
   BN_W(16, 2)
   BN_W(32, 1)
   BN_W(16, 4)
@@ -94,10 +109,14 @@ hipError_t launch_plain(const BurnArgs &a, int L, int S, int block_waves, hipStr
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_multi(const MultiArgs &m, int grid, hipStream_t stream) {
+hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream) {
   const size_t lds = 8 * (m.tab_doubles + (size_t)m.block_waves * m.wave_doubles);
-  hipLaunchKernelGGL((burn_multi_kernel<1>), dim3((unsigned)grid), dim3(64 * m.block_waves), lds,
-                     stream, m);
+  if (W == 2)
+    hipLaunchKernelGGL((burn_multi_kernel<2>), dim3((unsigned)grid), dim3(64 * m.block_waves),
+                       lds, stream, m);
+  else
+    hipLaunchKernelGGL((burn_multi_kernel<1>), dim3((unsigned)grid), dim3(64 * m.block_waves),
+                       lds, stream, m);
   return hipGetLastError();
 }
 

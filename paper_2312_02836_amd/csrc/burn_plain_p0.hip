@@ -8,6 +8,7 @@ hipError_t launch_plain_p0(const BurnArgs &a, int L, int S, int block_waves, hip
   BN_PLAIN_CASE(4, 1, 2)
   BN_PLAIN_CASE(4, 2, 2)
   BN_PLAIN_CASE(4, 4, 1)
+  BN_PLAIN_CASE(8, 1, 2)
   *found = false;
   return hipErrorInvalidValue;
 }

@@ -27,7 +27,7 @@ burn_source_kernel(BurnArgs a, int block_waves) {
 }  // namespace
 
 hipError_t launch_source(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
-#define BN_SRC(l, s)                                                                          \
+#define BN_SRC(l, s, w)                                                                          \
   if (L == l && S == s) {                                                                      \
     using SH = Shape<l, s>;                                                                    \
     const size_t lds =                                                                         \
@@ -35,14 +35,14 @@ hipError_t launch_source(const BurnArgs &a, int L, int S, int block_waves, hipSt
     const int64_t per = (int64_t)SH::CPW * block_waves;                                        \
     const int64_t blocks = (a.n_cells + per - 1) / per;                                        \
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;                                      \
-    hipLaunchKernelGGL((burn_source_kernel<l, s, 1>), dim3((unsigned)blocks),                  \
+    hipLaunchKernelGGL((burn_source_kernel<l, s, w>), dim3((unsigned)blocks),                  \
                        dim3(64 * block_waves), lds, stream, a, block_waves);                   \
     return hipGetLastError();                                                                  \
   }
-  BN_SRC(4, 4)
-  BN_SRC(16, 2)
-  BN_SRC(32, 1)
-  BN_SRC(64, 1)
+  BN_SRC(8, 1, 2)
+  BN_SRC(16, 1, 2)
+  BN_SRC(32, 1, 2)
+  BN_SRC(64, 1, 1)
 #undef BN_SRC
   return hipErrorInvalidValue;
 }

@@ -79,23 +79,27 @@ def test_plain_large_networks(gpu, oracle, which):
 
 
 def test_multi_mixed_parity_and_bitwise_plain(gpu, oracle):
-    """All four networks in one persistent launch: parity with the oracle,
-    and bitwise equality with plain launches of the same shapes."""
+    """All four networks in one persistent launch: parity with the oracle;
+    then, with every network's launch shape fixed to one the persistent and
+    the plain kernels share, bitwise equality with plain launches."""
     cfg, cells = _mixed()
     nets = [gpu.Network(s) for s in cfg.networks]
     outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cells)], cfg.t_end,
                           RTOL, ATOL)
-    multi_shapes = {(4, 4), (16, 2), (32, 1), (64, 1)}
     for n, spec, c, out in zip(nets, cfg.networks, cells, outs):
         g = _host(out)
         print(spec.name, flush=True)
         _check(g, oracle, spec, c, cfg.t_end,
                min_counter_equal=0.98 if spec.n_species >= 50 else 0.99)
-        L, S, _ = n.get_launch()
-        if (L, S) in multi_shapes:
-            p = _host(gpu.burn(n, c.Y, c.rho, c.T, cfg.t_end, RTOL, ATOL))
-            for a, b in zip(g, p):
-                assert np.array_equal(a, b, equal_nan=True)
+    for n, spec in zip(nets, cfg.networks):
+        n.set_launch(32 if spec.n <= 32 else 64, 1, 0)
+    outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cells)], cfg.t_end,
+                          RTOL, ATOL)
+    for n, c, out in zip(nets, cells, outs):
+        g = _host(out)
+        p = _host(gpu.burn(n, c.Y, c.rho, c.T, cfg.t_end, RTOL, ATOL))
+        for a, b in zip(g, p):
+            assert np.array_equal(a, b, equal_nan=True)
     for n in nets:
         n.close()
 
@@ -181,4 +185,27 @@ def test_autotune_then_burn(gpu, oracle):
     g = _host(gpu.burn(net, sub.Y, sub.rho, sub.T, cfg.t_end, RTOL, ATOL))
     _check(g, oracle, spec, sub, cfg.t_end)
     net.set_launch(0, 0, 0)
+    net.close()
+
+
+def test_every_plain_shape_via_set_launch(gpu, oracle):
+    """Every compiled plain shape that holds the 14-component system, chosen
+    with bn_network_set_launch, against one oracle run."""
+    shapes = [(4, 4), (8, 2), (8, 4), (16, 1), (16, 2), (32, 1), (16, 4), (32, 2), (64, 1)]
+    cfg = synth.config(2, n_cells=300)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = gpu.Network(spec)
+    o = _oracle(oracle, spec, cells, cfg.t_end)
+    for L, S in shapes:
+        net.set_launch(L, S, 0)
+        assert net.get_launch()[:2] == (L, S)
+        g = _host(gpu.burn(net, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL))
+        print("shape", L, S, flush=True)
+
+        def tight(idx):
+            r = oracle.burn(oracle.OracleNet(spec), cells.subset(idx), cfg.t_end, RTOL * 1e-4,
+                            ATOL * 1e-4)
+            return r[0], r[1]
+
+        assert_parity(g, o, RTOL, ATOL, tight=tight)
     net.close()
