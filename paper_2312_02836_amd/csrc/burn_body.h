@@ -195,20 +195,6 @@ __device__ __forceinline__ int gor(int v) {
   }
 }
 
-// Max of v, ties to the smallest p (a total order: all lanes agree).
-template <int G, int LV = 0>
-__device__ __forceinline__ void gargmax(double &v, int &p) {
-  if constexpr (LV < n_levels<G>()) {
-    const double ov = xch<G, LV>(v);
-    const int op = xch_i<G, LV>(p);
-    if (ov > v || (ov == v && op < p)) {
-      v = ov;
-      p = op;
-    }
-    gargmax<G, LV + 1>(v, p);
-  }
-}
-
 // Arg-max with a payload: max of v, ties to the smallest p; w travels with
 // the winner.
 template <int G, int LV = 0>
@@ -271,6 +257,7 @@ struct Shape {
   static constexpr int CPW = 64 / L;
   static constexpr int FL = NP;       // factor lanes per cell (one row each)
   static constexpr int FC = 64 / NP;  // cells per factorization pass
+  static constexpr int ECH = 4;  // elimination columns per LDS batch
   static_assert(NP == 4 || NP == 8 || NP == 16 || NP == 32 || NP == 64, "NP must be a power of 2");
   static constexpr int DS = DROWS * NP + 4;  // history stride per cell
   static constexpr int YS = NP + 4;          // exchange-vector stride per cell
@@ -338,16 +325,17 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
                                           int64_t first_cell, unsigned long long *queue) {
   using SH = Shape<L, S>;
   constexpr int NP = SH::NP, CPW = SH::CPW, FL = SH::FL, FC = SH::FC;
-  constexpr int DS = SH::DS, YS = SH::YS;
+  constexpr int DS = SH::DS, YS = SH::YS, ECH = SH::ECH;
 
   const NetTables &nt = a.net;
-  const int N = nt.N, R = nt.R, n = nt.n;
+  const int N = nt.N, R = nt.R;
+  int n = nt.n;  // re-derived opaquely in every iteration, like q
   const int MS = SH::ms(n);
   const int MROWS = SH::rows(n);
   const size_t FB = SH::fb(n);
 
   const int lane = threadIdx.x & 63;
-  const int q = lane % L;
+  int q = lane % L;  // re-derived opaquely in every iteration (see below)
   const int cw = lane / L;
   const int64_t C = a.n_cells;
 
@@ -604,6 +592,13 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   if constexpr (!QUEUE) load_cell(first_cell);
 
   while (true) {
+    // The lane index is made opaque to the compiler once per iteration, so
+    // the many lane predicates of the unrolled loops (q > K, q == K, ...) are
+    // computed where they are used instead of being hoisted out of this loop
+    // and kept live as scalar masks, which exceeds the scalar registers and
+    // spills them.  The same holds for the uniform tests K < n.
+    asm volatile("" : "+v"(q));
+    asm volatile("" : "+s"(n));
     // ---------------- 0: write a finished cell, take the next one ----------------
     if constexpr (QUEUE) {
       if (phase == PH_DONE) {
@@ -718,7 +713,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       wave_lds_sync();
       // (b) factor layout: slot fj = lane / FL, row fi = lane % FL; in the
       // compact layout the rows fi >= n of a padded system take no part
-      const int fj = lane / FL, fi = lane % FL;
+      int flane = lane;
+      asm volatile("" : "+v"(flane));
+      const int fj = flane / FL, fi = flane % FL;
       int fsel = -1;
 #pragma unroll
       for (int j = 0; j < FC; ++j)
@@ -846,8 +843,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         double v = -2.0;
         int nan_k = 0;
         const bool cand = frow && pos >= K;
+        double mk = 0.0;
         if (cand) {
-          v = fabs(Mrow[K]);
+          mk = Mrow[K];
+          v = fabs(mk);
           if (v != v) {
             if (pos == K) nan_k = 1;
             v = -1.0;
@@ -866,9 +865,27 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         const double rinv = 1.0 / P[K];
         if (frow && pos == K) fdinv = rinv;
         if (frow && pos > K) {
-          const double l = Mrow[K] * rinv;
+          const double l = mk * rinv;
           Mrow[K] = l;
-          for (int j = K + 1; j < n; ++j) Mrow[j] -= l * P[j];
+          // chunks of ECH columns: all loads of a chunk are issued before the
+          // first use, so the LDS latency is paid once per chunk
+          for (int j0 = K + 1; j0 < n; j0 += ECH) {
+            double a[ECH], b[ECH];
+#pragma unroll
+            for (int u = 0; u < ECH; ++u) {
+              if (j0 + u < n) {
+                a[u] = Mrow[j0 + u];
+                b[u] = P[j0 + u];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < ECH; ++u) {
+              if (j0 + u < n) {
+                a[u] -= l * b[u];
+                Mrow[j0 + u] = a[u];
+              }
+            }
+          }
         }
         wave_lds_sync();
       }
