@@ -73,18 +73,21 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ---- cross-lane operations inside an aligned group of G lanes --------------
 
+// DPP moves with bound_ctrl set: a lane whose source lane is inactive reads
+// 0 (every control used here addresses a lane of the same row), so no old
+// value has to be materialised in the destination first.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
   const long long r = ((long long)(unsigned)lo) | ((long long)hi << 32);
   return __builtin_bit_cast(double, r);
 }
 
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ double readlane_f64(double v, int src) {
@@ -337,7 +340,18 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   const int lane = threadIdx.x & 63;
   int q = lane % L;  // re-derived opaquely in every iteration (see below)
   const int cw = lane / L;
-  const int64_t C = a.n_cells;
+  // Launch constants used inside the cell loop.  Each is made opaque once,
+  // so it lives in scalar registers of its own: loaded as part of one wide
+  // kernel-argument load, a value would otherwise tie the whole load's
+  // registers together, and a spill of it reloads all of them.
+  int64_t C = a.n_cells;
+  double rtol = a.rtol, atol = a.atol, t_end = a.t_end;
+  double *gY = a.Y, *gT = a.T;
+  const double *grho = a.rho;
+  int32_t *gst = a.status, *gcnt = a.counters;
+  int max_steps = a.max_steps;
+  asm volatile("" : "+s"(C), "+s"(rtol), "+s"(atol), "+s"(t_end));
+  asm volatile("" : "+s"(gY), "+s"(gT), "+s"(grho), "+s"(gst), "+s"(gcnt), "+s"(max_steps));
 
   double *Dl = wb + (size_t)cw * DS;  // this cell's history, [DROWS][NP]
   double *ybuf = wb + (size_t)CPW * DS + (size_t)cw * YS;
@@ -345,7 +359,6 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   double *fbase = wb + (size_t)CPW * DS + 2 * (size_t)CPW * YS;
   double *fsc = fbase + (size_t)FC * FB;
 
-  const double rtol = a.rtol, atol = a.atol, t_end = a.t_end;
   const double *s_rtab = tb.rtab, *s_emult = tb.emult, *s_q = tb.q, *s_qcv = tb.qcv;
   const int *s_rsp = tb.rsp, *s_rout = tb.rout;
 
@@ -533,8 +546,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const int i = comp(s);
-        if (i < N) a.Y[(int64_t)i * C + cell] = Dl[i];
-        else if (i == N) a.T[cell] = Dl[i];
+        if (i < N) gY[(int64_t)i * C + cell] = Dl[i];
+        else if (i == N) gT[cell] = Dl[i];
       }
     }
     if constexpr (REC) {
@@ -542,11 +555,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         a.sched[cell * a.sched_stride] = (status == ST_OK) ? (double)cnt[CNT_STEPS] : -1.0;
     }
     if (q == 0) {
-      if (a.status) a.status[cell] = status;
-      if (a.counters) {
+      if (gst) gst[cell] = status;
+      if (gcnt) {
 #pragma unroll
         for (int c = 0; c < 8; ++c)
-          a.counters[(int64_t)c * C + cell] = (status == ST_BAD_INPUT) ? 0 : cnt[c];
+          gcnt[(int64_t)c * C + cell] = (status == ST_BAD_INPUT) ? 0 : cnt[c];
       }
     }
   };
@@ -558,7 +571,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       return;
     }
     cell = c;
-    rho = a.rho[cell];
+    rho = grho[cell];
     status = 0;
     write_state = 0;
     k = 1;
@@ -569,7 +582,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       const int i = comp(s);
-      yv[s] = (i < N) ? a.Y[(int64_t)i * C + cell] : ((i == N) ? a.T[cell] : 0.0);
+      yv[s] = (i < N) ? gY[(int64_t)i * C + cell] : ((i == N) ? gT[cell] : 0.0);
       if constexpr (SRC) srcv[s] = (i < n) ? a.src[(int64_t)i * C + cell] : 0.0;
     }
     int bad = !(rho > 0.0) || !isfinite(rho);
@@ -626,7 +639,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 
     // ---------------- A: start of a step attempt ----------------
     if (phase == PH_NEWTON && need_attempt) {
-      if (new_step && cnt[CNT_STEPS] >= a.max_steps) {
+      if (new_step && cnt[CNT_STEPS] >= max_steps) {
         status = 1;
         phase = PH_DONE;
       } else {
