@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_body.h",
+                  "paper_2312_02836_amd/csrc/bn_math.h",
                   "paper_2312_02836_amd/csrc/burn_plain.h",
                   "paper_2312_02836_amd/csrc/burn_multi.hip",
                   "paper_2312_02836_amd/csrc/burn_internal.h"]

@@ -79,7 +79,7 @@ __device__ __forceinline__ TPow tpow(double T) {
   p.t13 = cbrt(T);
   p.tm13 = 1.0 / p.t13;
   p.t53 = T * p.t13 * p.t13;
-  p.lnT = log(T);
+  p.lnT = bn_log(T);
   p.tinv = 1.0 / T;
   return p;
 }

@@ -31,6 +31,7 @@
 //    so cells in different phases still share the RHS and solve instructions.
 #pragma once
 
+#include "bn_math.h"
 #include "burn_internal.h"
 
 #include <math.h>
@@ -450,7 +451,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     const double t13 = cbrt(T);
     const double tm13 = 1.0 / t13;
     const double t53 = T * t13 * t13;
-    const double lnT = log(T);
+    const double lnT = bn_log(T);
     const double tinv = 1.0 / T;
     double G = 0.0;
     if constexpr (SCR) {
@@ -760,7 +761,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         const double t13 = cbrt(T);
         const double tm13 = 1.0 / t13;
         const double t53 = T * t13 * t13;
-        const double lnT = log(T);
+        const double lnT = bn_log(T);
         const double tinv = 1.0 / T;
         if constexpr (SCR) {
           for (int j = 0; j < N; ++j) fS += nt.wsq[j] * fy[j];
@@ -1078,7 +1079,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           }
           err = wrms(e1, isc);
           if (err > 1.0) {
-            double fct = kSafety * pow(err, -1.0 / (double)(k + 1));
+            double fct = kSafety * exp(bn_log(err) * (-1.0 / (double)(k + 1)));
             if (fct < kMinFactor) fct = kMinFactor;
             h *= fct;
             pend = fct;
@@ -1125,21 +1126,23 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               ep_acc = gsum<L>(ep_acc);
               const double em = (k > 1) ? sqrt(em_acc / (double)n) : INFINITY;
               const double ep = (k < KMAX) ? sqrt(ep_acc / (double)n) : INFINITY;
-              const double fm = pow(em, -1.0 / (double)k);
-              const double f0 = pow(err, -1.0 / (double)(k + 1));
-              const double fp = pow(ep, -1.0 / (double)(k + 2));
-              double best = f0;
+              // the factors norm^(-1/(order+1)) of orders k-1, k, k+1,
+              // compared by their logarithms; one exponential for the best
+              const double lm = bn_log(em) * (-1.0 / (double)k);
+              const double l0 = bn_log(err) * (-1.0 / (double)(k + 1));
+              const double lp = bn_log(ep) * (-1.0 / (double)(k + 2));
+              double best = l0;
               int dk = 0;
-              if (fm > best) {
-                best = fm;
+              if (lm > best) {
+                best = lm;
                 dk = -1;
               }
-              if (fp > best) {
-                best = fp;
+              if (lp > best) {
+                best = lp;
                 dk = 1;
               }
               k += dk;
-              double fct = kSafety * best;
+              double fct = kSafety * exp(best);
               if (fct > kMaxFactor) fct = kMaxFactor;
               h *= fct;
               pend = fct;
