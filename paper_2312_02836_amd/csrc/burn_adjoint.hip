@@ -238,9 +238,9 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
           v = -1.0;
         }
       }
-      int bp = cand ? pos : (1 << 30);
-      int prow_i = lane;
-      gargmax3<64>(v, bp, prow_i);
+      int key = cand ? ((pos << 8) | lane) : 0x7fffffff;
+      gargmax_key<64>(v, key);
+      const int bp = key >> 8, prow_i = key & 255;
       nan_k = gor<64>(nan_k);
       if (!(v > 0.0) || nan_k) sing = 1;
       if (own) {

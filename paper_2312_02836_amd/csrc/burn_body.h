@@ -199,23 +199,6 @@ __device__ __forceinline__ int gor(int v) {
   }
 }
 
-// Arg-max with a payload: max of v, ties to the smallest p; w travels with
-// the winner.
-template <int G, int LV = 0>
-__device__ __forceinline__ void gargmax3(double &v, int &p, int &w) {
-  if constexpr (LV < n_levels<G>()) {
-    const double ov = xch<G, LV>(v);
-    const int op = xch_i<G, LV>(p);
-    const int ow = xch_i<G, LV>(w);
-    if (ov > v || (ov == v && op < p)) {
-      v = ov;
-      p = op;
-      w = ow;
-    }
-    gargmax3<G, LV + 1>(v, p, w);
-  }
-}
-
 // Calls f.template operator()<I>() for I = 0..N-1 (compile-time indices).
 template <int N>
 struct Unroll {
@@ -230,6 +213,23 @@ struct Unroll<0> {
   template <typename F>
   __device__ __forceinline__ static void run(F &&) {}
 };
+
+// Arg-max of v over the group, ties to the smallest key: the maximum of v
+// first (NaN-free inputs), then the smallest key among the lanes that hold
+// it.  Two plain reductions instead of a lexicographic compare per level.
+template <int G>
+__device__ __forceinline__ void gargmax_key(double &v, int &key) {
+  double m = v;
+  Unroll<n_levels<G>()>::run([&]<int LV>() __attribute__((always_inline)) {
+    m = fmax(m, xch<G, LV>(m));
+  });
+  int k = (v == m) ? key : 0x7fffffff;
+  Unroll<n_levels<G>()>::run([&]<int LV>() __attribute__((always_inline)) {
+    k = min(k, xch_i<G, LV>(k));
+  });
+  v = m;
+  key = k;
+}
 
 
 
@@ -866,9 +866,12 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             v = -1.0;
           }
         }
-        int bp = cand ? pos : (1 << 30);
-        int prow_i = fi;  // physical row of the pivot (payload of the arg-max)
-        gargmax3<FL>(v, bp, prow_i);
+        // key: position, then the physical row (the payload); positions of
+        // candidates are distinct, so the smallest key is the first position
+        int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
+        gargmax_key<FL>(v, key);
+        const int bp = key >> 8;
+        const int prow_i = key & 255;  // physical row of the pivot
         nan_k = gor<FL>(nan_k);
         if (!(v > 0.0) || nan_k) fsing = 1;
         if (frow) {
