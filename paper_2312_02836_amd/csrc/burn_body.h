@@ -330,6 +330,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   using SH = Shape<L, S>;
   constexpr int NP = SH::NP, CPW = SH::CPW, FL = SH::FL, FC = SH::FC;
   constexpr int DS = SH::DS, YS = SH::YS, ECH = SH::ECH;
+  // one-slot shapes (a cell per group, NP = L) factor in registers
+  constexpr bool REG_LU = S == 1 && NP <= 16;
 
   const NetTables &nt = a.net;
   const int N = nt.N, R = nt.R;
@@ -701,13 +703,21 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     unsigned long long wmask = __ballot(want && q == 0);
     while (wmask) {
       int sel[FC];
+      if constexpr (REG_LU) {
+        // one cell per slot (FC == CPW): every cell factors in its own
+        // group's lanes, so the rows can stay in the owners' registers
 #pragma unroll
-      for (int j = 0; j < FC; ++j) {
-        if (wmask) {
-          sel[j] = (__ffsll((long long)wmask) - 1) / L;
-          wmask &= wmask - 1;
-        } else {
-          sel[j] = -1;
+        for (int j = 0; j < FC; ++j) sel[j] = ((wmask >> (j * L)) & 1) ? j : -1;
+        wmask = 0;
+      } else {
+#pragma unroll
+        for (int j = 0; j < FC; ++j) {
+          if (wmask) {
+            sel[j] = (__ffsll((long long)wmask) - 1) / L;
+            wmask &= wmask - 1;
+          } else {
+            sel[j] = -1;
+          }
         }
       }
       // (a) the selected cells publish y_J, c and rho
@@ -846,65 +856,125 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       }
       jbad = gor<FL>(jbad);
       wave_lds_sync();
-      // (c) LU with partial pivoting on the matrix in LDS, one row per lane.
-      // Rows are not moved: `pos` is the position the row would hold after the
-      // textbook row swaps (the first largest |pivot| in position order wins).
+      // (c) LU with partial pivoting, one row per lane.  Rows are not moved:
+      // `pos` is the position the row would hold after the textbook row swaps
+      // (the first largest |pivot| in position order wins).
       int pos = fi;
       int fsing = 0;
       double fdinv = 1.0;
-      double *Mrow = fM + (frow ? fi : 0) * MS;
-      for (int K = 0; K < n; ++K) {
-        double v = -2.0;
-        int nan_k = 0;
-        const bool cand = frow && pos >= K;
-        double mk = 0.0;
-        if (cand) {
-          mk = Mrow[K];
-          v = fabs(mk);
-          if (v != v) {
-            if (pos == K) nan_k = 1;
-            v = -1.0;
-          }
-        }
-        // key: position, then the physical row (the payload); positions of
-        // candidates are distinct, so the smallest key is the first position
-        int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
-        gargmax_key<FL>(v, key);
-        const int bp = key >> 8;
-        const int prow_i = key & 255;  // physical row of the pivot
-        nan_k = gor<FL>(nan_k);
-        if (!(v > 0.0) || nan_k) fsing = 1;
-        if (frow) {
-          if (pos == K) pos = bp;
-          else if (pos == bp) pos = K;
-        }
-        const double *P = fM + prow_i * MS;
-        const double rinv = 1.0 / P[K];
-        if (frow && pos == K) fdinv = rinv;
-        if (frow && pos > K) {
-          const double l = mk * rinv;
-          Mrow[K] = l;
-          // chunks of ECH columns: all loads of a chunk are issued before the
-          // first use, so the LDS latency is paid once per chunk
-          for (int j0 = K + 1; j0 < n; j0 += ECH) {
-            double a[ECH], b[ECH];
+      if constexpr (REG_LU) {
+        // The row lives in the lane's LU registers (slot fj is the lane's own
+        // cell); per pivot the pivot row's remaining entries go through the
+        // y_J area of the slot, which is free once the Jacobian is built.
+        const bool mine = fsel >= 0;
+        if (mine) {
+          const double *mr = fM + (frow ? fi : 0) * MS;
 #pragma unroll
-            for (int u = 0; u < ECH; ++u) {
-              if (j0 + u < n) {
-                a[u] = Mrow[j0 + u];
-                b[u] = P[j0 + u];
-              }
-            }
-#pragma unroll
-            for (int u = 0; u < ECH; ++u) {
-              if (j0 + u < n) {
-                a[u] -= l * b[u];
-                Mrow[j0 + u] = a[u];
-              }
-            }
-          }
+          for (int j = 0; j < NP; ++j)
+            LU[0][j] = (frow && (!SH::COMPACT || j < n)) ? mr[j] : 0.0;
         }
         wave_lds_sync();
+        Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
+          if (K < n) {
+            double v = -2.0;
+            int nan_k = 0;
+            const bool cand = mine && frow && pos >= K;
+            if (cand) {
+              v = fabs(LU[0][K]);
+              if (v != v) {
+                if (pos == K) nan_k = 1;
+                v = -1.0;
+              }
+            }
+            int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
+            gargmax_key<FL>(v, key);
+            nan_k = gor<FL>(nan_k);
+            if (!(v > 0.0) || nan_k) fsing = 1;
+            const int bp = key >> 8;
+            if (frow) {
+              if (pos == K) pos = bp;
+              else if (pos == bp) pos = K;
+            }
+            if (mine && fi == (key & 255)) {
+#pragma unroll
+              for (int j = K; j < NP; ++j) fy[j] = LU[0][j];
+            }
+            wave_lds_sync();
+            if (mine && frow) {
+              const double rinv = 1.0 / fy[K];
+              if (pos == K) fdinv = rinv;
+              if (pos > K) {
+                const double l = LU[0][K] * rinv;
+                LU[0][K] = l;
+#pragma unroll
+                for (int j = K + 1; j < NP; ++j) LU[0][j] -= l * fy[j];
+              }
+            }
+            wave_lds_sync();
+          }
+        });
+        // rows to LDS in position order, for the hand-over to the solves
+        if (mine && frow) {
+          double *dst = fM + pos * MS;
+#pragma unroll
+          for (int j = 0; j < NP; ++j)
+            if (!SH::COMPACT || j < n) dst[j] = LU[0][j];
+        }
+      } else {
+        double *Mrow = fM + (frow ? fi : 0) * MS;
+        for (int K = 0; K < n; ++K) {
+          double v = -2.0;
+          int nan_k = 0;
+          const bool cand = frow && pos >= K;
+          double mk = 0.0;
+          if (cand) {
+            mk = Mrow[K];
+            v = fabs(mk);
+            if (v != v) {
+              if (pos == K) nan_k = 1;
+              v = -1.0;
+            }
+          }
+          // key: position, then the physical row (the payload); positions of
+          // candidates are distinct, so the smallest key is the first position
+          int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
+          gargmax_key<FL>(v, key);
+          const int bp = key >> 8;
+          const int prow_i = key & 255;  // physical row of the pivot
+          nan_k = gor<FL>(nan_k);
+          if (!(v > 0.0) || nan_k) fsing = 1;
+          if (frow) {
+            if (pos == K) pos = bp;
+            else if (pos == bp) pos = K;
+          }
+          const double *P = fM + prow_i * MS;
+          const double rinv = 1.0 / P[K];
+          if (frow && pos == K) fdinv = rinv;
+          if (frow && pos > K) {
+            const double l = mk * rinv;
+            Mrow[K] = l;
+            // chunks of ECH columns: all loads of a chunk are issued before the
+            // first use, so the LDS latency is paid once per chunk
+            for (int j0 = K + 1; j0 < n; j0 += ECH) {
+              double a[ECH], b[ECH];
+#pragma unroll
+              for (int u = 0; u < ECH; ++u) {
+                if (j0 + u < n) {
+                  a[u] = Mrow[j0 + u];
+                  b[u] = P[j0 + u];
+                }
+              }
+#pragma unroll
+              for (int u = 0; u < ECH; ++u) {
+                if (j0 + u < n) {
+                  a[u] -= l * b[u];
+                  Mrow[j0 + u] = a[u];
+                }
+              }
+            }
+          }
+          wave_lds_sync();
+        }
       }
       // (d) the factors stay in LDS; publish position -> row and 1/U_pp
       double *aux = fM + (size_t)MROWS * MS;
@@ -930,7 +1000,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             // them stays inside this slot (the auxiliary rows follow)
             dinv[s] = saux[p];
             ridx[s] = (int)saux[NP + p];
-            const double *row = src + ridx[s] * MS;
+            // register factorization: rows stored by position
+            const double *row = src + (REG_LU ? p : ridx[s]) * MS;
 #pragma unroll
             for (int j = 0; j < NP; ++j) LU[s][j] = row[j];
           } else {
