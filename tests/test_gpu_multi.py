@@ -209,3 +209,41 @@ def test_every_plain_shape_via_set_launch(gpu, oracle):
 
         assert_parity(g, o, RTOL, ATOL, tight=tight)
     net.close()
+
+
+def _sampled(oracle, spec, cells, t_end, out, n_sample, seed, min_counter_equal=0.99):
+    g = _host(out)
+    idx = np.sort(np.random.default_rng(seed).choice(cells.n_cells, n_sample, replace=False))
+    sub = cells.subset(idx)
+    gs = (g[0][:, idx], g[1][idx], g[2][idx], g[3][:, idx])
+    print(spec.name, "sample", n_sample, "of", cells.n_cells, flush=True)
+    _check(gs, oracle, spec, sub, t_end, min_counter_equal=min_counter_equal)
+    assert np.all(g[2] == 0)
+
+
+def test_mixed4_full_size_sampled(gpu, oracle):
+    """The mixed benchmark workload as bench.py times it: four networks,
+    65,536 cells each, one persistent launch with the default shapes; the
+    oracle recomputes a seeded sample of each network's cells one by one."""
+    cfg = synth.config(4)
+    nets = [gpu.Network(s) for s in cfg.networks]
+    outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cfg.cells)], cfg.t_end,
+                          RTOL, ATOL)
+    for i, (spec, c, out) in enumerate(zip(cfg.networks, cfg.cells, outs)):
+        _sampled(oracle, spec, c, cfg.t_end, out, 384, i,
+                 min_counter_equal=0.98 if spec.n_species >= 50 else 0.99)
+    for n in nets:
+        n.close()
+
+
+def test_synth50_full_size_sampled(gpu, oracle):
+    """50 species / 150 reactions, 1,048,576 cells with T log-uniform in
+    [0.8, 6] (a 4x spread of step counts) in one persistent launch; a seeded
+    sample of 256 cells recomputed by the oracle."""
+    cfg = synth.config(3)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    assert cells.n_cells == 1048576
+    net = gpu.Network(spec)
+    out = gpu.burn_multi([(net, cells.Y, cells.rho, cells.T)], cfg.t_end, RTOL, ATOL)[0]
+    _sampled(oracle, spec, cells, cfg.t_end, out, 256, 7, min_counter_equal=0.98)
+    net.close()
