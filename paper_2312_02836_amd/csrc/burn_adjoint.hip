@@ -123,9 +123,12 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
 }
 
 // One cell per wave.  BACKWARD = false: replay from y(0), write the
-// checkpoints, the end state and E.  BACKWARD = true: reverse sweep.
-template <bool BACKWARD>
-__global__ void __launch_bounds__(256) adjoint_kernel(AdjArgs a) {
+// checkpoints, the end state and E.  BACKWARD = true: reverse sweep.  W is
+// the waves per SIMD the registers are budgeted for (3 when the LDS lets
+// three waves per SIMD reside, else 2).
+template <bool BACKWARD, int W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
+adjoint_kernel(AdjArgs a) {
   extern __shared__ double smem[];
   load_tables(a.net, a.log_mult, smem);
   __syncthreads();
@@ -606,16 +609,23 @@ hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipSt
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_t stream) {
+hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
+                          hipStream_t stream) {
   const size_t lds = adjoint_lds_bytes(a.net.R, a.net.n, waves);
   const int64_t blocks = (a.n_cells + waves - 1) / waves;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (backward)
-    hipLaunchKernelGGL((adjoint_kernel<true>), dim3((unsigned)blocks), dim3(64 * waves), lds,
-                       stream, a);
-  else
-    hipLaunchKernelGGL((adjoint_kernel<false>), dim3((unsigned)blocks), dim3(64 * waves), lds,
-                       stream, a);
+  const dim3 grid((unsigned)blocks), block(64 * waves);
+  if (backward) {
+    if (simd_waves >= 3)
+      hipLaunchKernelGGL((adjoint_kernel<true, 3>), grid, block, lds, stream, a);
+    else
+      hipLaunchKernelGGL((adjoint_kernel<true, 2>), grid, block, lds, stream, a);
+  } else {
+    if (simd_waves >= 3)
+      hipLaunchKernelGGL((adjoint_kernel<false, 3>), grid, block, lds, stream, a);
+    else
+      hipLaunchKernelGGL((adjoint_kernel<false, 2>), grid, block, lds, stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -773,6 +773,18 @@ int adj_waves(const bn_network *net) {
   return w;
 }
 
+// register budget of the adjoint kernels: three waves per SIMD when the LDS
+// lets twelve waves reside on a CU, else two
+int adj_simd_waves(const bn_network *net, int waves) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  DeviceLimits lim;
+  if (device_limits(dev, &lim)) return 2;
+  const size_t per_block = bn::adjoint_lds_bytes(net->R, net->n, waves);
+  const size_t resident = per_block ? (lim.lds_cu / per_block) * (size_t)waves : 0;
+  return resident >= 12 ? 3 : 2;
+}
+
 }  // namespace
 
 size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells,
@@ -833,7 +845,8 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
   a.Tout = T_out;
   a.Eout = E_out;
   a.iters = replay_iters;
-  e = bn::launch_adjoint(a, false, adj_waves(net), st);
+  const int aw = adj_waves(net);
+  e = bn::launch_adjoint(a, false, aw, adj_simd_waves(net, aw), st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("replay launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;
 }
@@ -857,7 +870,9 @@ int burn_batch_adjoint_backward(const bn_network *net, int64_t n_cells, const do
   a.gY = gY;
   a.gE = gE;
   a.grad = grad;
-  const hipError_t e = bn::launch_adjoint(a, true, adj_waves(net), static_cast<hipStream_t>(stream));
+  const int aw = adj_waves(net);
+  const hipError_t e =
+      bn::launch_adjoint(a, true, aw, adj_simd_waves(net, aw), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(BN_EHIP, std::string("adjoint launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;
 }

@@ -119,7 +119,9 @@ size_t adjoint_sched_stride(int cap);  // doubles per cell
 int adjoint_n_ckpt(int cap);
 size_t adjoint_lds_bytes(int R, int n, int waves);
 hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
-hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, hipStream_t stream);
+// simd_waves: 3 or 2, the register budget of the kernel instance to launch
+hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
+                          hipStream_t stream);
 
 // Plain launch with a constant per-cell source (a.src != nullptr); shapes
 // of MULTI_SHAPES_2.
