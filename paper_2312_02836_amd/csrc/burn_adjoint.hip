@@ -87,7 +87,7 @@ __device__ __forceinline__ TPow tpow(double T) {
 __device__ __forceinline__ double rate_and_slots(const Tabs &tb, int r, const TPow &tp,
                                                  const double *ybuf, double rho, bool want_g,
                                                  double g[4]) {
-  const double *c = tb.rtab + 8 * (size_t)r;
+  const Coef c = coef_of(tb.rtab, r);
   const double expo = c[0] + c[1] * tp.tinv + c[2] * tp.tm13 + c[3] * tp.t13 + c[4] * tp.T +
                       c[5] * tp.t53 + c[6] * tp.lnT;
   const int *sp = tb.rsp + 4 * r;

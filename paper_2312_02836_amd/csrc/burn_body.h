@@ -236,18 +236,34 @@ __device__ __forceinline__ void gargmax_key(double &v, int &key) {
 // ---------------------------------------------------------------------------
 // LDS layout.  Per workgroup, the network tables (every array starts on a
 // 16-byte boundary, so a reaction's output list is one aligned 16-byte pair):
-//   rtab[8R] (doubles) | rout[8R] rsp[4R] (ints) | emult[R] q[R] qcv[R] (doubles)
+//   rtab[8 Rb] (doubles, Rb = R rounded up to 32; see coef_of) | rout[8R] rsp[4R] (ints)
+//   | emult[R] q[R] qcv[R] (doubles)
 // then one area per wave:
 //   D[CPW][DS] ybuf[CPW][YS] facc[CPW][YS] fslot[FC][FB] fsc[FC][4]
 // with FB = NP + n*MS + 2*NP + 1 doubles per factorization slot: y_J, the
 // Newton matrix (n rows, odd row stride MS, later the factors in place) and
 // two auxiliary rows (reciprocal pivots and row indices by position).  The
-// per-cell strides DS and YS are 4 doubles more than a multiple of 16 and MS
-// is odd, so the cells of a wave (and the rows of a matrix) fall in different
-// LDS banks.
+// per-cell strides DS and YS place the cells of a half-wave on disjoint LDS
+// banks (see Shape) and MS is odd, so the rows of a matrix fall in
+// different banks.
 // ---------------------------------------------------------------------------
 
-__host__ __device__ inline size_t tab_doubles_of(int R) { return 17 * (size_t)R; }
+// The rate coefficients are stored in blocks of 32 reactions, coefficient
+// by coefficient: reaction r = 32a + b has coefficient k at
+// ((8a + k) * 32 + b).  Lanes working on consecutive reactions then read
+// consecutive doubles (no bank conflicts), and the eight coefficients of a
+// reaction sit at constant offsets from its first.
+__host__ __device__ inline size_t rblk_of(int R) { return ((size_t)R + 31) & ~(size_t)31; }
+__host__ __device__ inline size_t tab_doubles_of(int R) { return 8 * rblk_of(R) + 9 * (size_t)R; }
+
+// coefficient k of one reaction: c[k]
+struct Coef {
+  const double *p;
+  __device__ __forceinline__ double operator[](int k) const { return p[32 * k]; }
+};
+__device__ __forceinline__ Coef coef_of(const double *rtab, int r) {
+  return Coef{rtab + ((size_t)(r >> 5) * 256 + (r & 31))};
+}
 
 template <int L, int S>
 struct Shape {
@@ -263,8 +279,18 @@ struct Shape {
   static constexpr int FC = 64 / NP;  // cells per factorization pass
   static constexpr int ECH = 4;  // elimination columns per LDS batch
   static_assert(NP == 4 || NP == 8 || NP == 16 || NP == 32 || NP == 64, "NP must be a power of 2");
-  static constexpr int DS = DROWS * NP + 4;  // history stride per cell
-  static constexpr int YS = NP + 4;          // exchange-vector stride per cell
+  // Per-cell strides.  A wave's LDS access is served half a wave (32 lanes)
+  // at a time; the 32/L cells of a half-wave each touch 2L consecutive banks
+  // (L consecutive doubles).  A cell stride that is an odd multiple of L
+  // doubles puts them on disjoint banks.  Groups of 32 or 64 lanes fill a
+  // half-wave alone.
+  static constexpr int stride_for(int base) {
+    if (L >= 32) return base + 4;
+    const int m = (base + L - 1) / L;
+    return (m % 2 ? m : m + 1) * L;
+  }
+  static constexpr int DS = stride_for(DROWS * NP);  // history stride per cell
+  static constexpr int YS = stride_for(NP);          // exchange-vector stride per cell
   __host__ __device__ static size_t fb(int n) {
     return (size_t)NP + (size_t)rows(n) * ms(n) + 2 * (size_t)NP + 1;
   }
@@ -281,7 +307,7 @@ struct Tabs {
 __device__ __forceinline__ Tabs tabs_at(double *smem, int R) {
   Tabs t;
   t.rtab = smem;
-  t.rout = reinterpret_cast<const int *>(smem + 8 * (size_t)R);
+  t.rout = reinterpret_cast<const int *>(smem + 8 * rblk_of(R));
   t.rsp = t.rout + 8 * R;
   t.emult = reinterpret_cast<const double *>(t.rsp + 4 * R);
   t.q = t.emult + R;
@@ -295,14 +321,15 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
                                             double *smem) {
   const int R = nt.R;
   double *rtab = smem;
-  int *rout = reinterpret_cast<int *>(smem + 8 * (size_t)R);
+  int *rout = reinterpret_cast<int *>(smem + 8 * rblk_of(R));
   int *rsp = rout + 8 * R;
   double *emult = reinterpret_cast<double *>(rsp + 4 * R);
   double *q = emult + R;
   double *qcv = q + R;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int i = tid; i < 8 * R; i += nth) {
-    rtab[i] = nt.rtab[i];
+    const int r = i >> 3, k = i & 7;
+    rtab[((r >> 5) * 8 + k) * 32 + (r & 31)] = nt.rtab[i];
     rout[i] = nt.rout[i];
   }
   for (int i = tid; i < R; i += nth) {
@@ -464,7 +491,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     }
     double heat = 0.0;
     auto one = [&](int r) __attribute__((always_inline)) {
-      const double *c = s_rtab + 8 * (size_t)r;
+      const Coef c = coef_of(s_rtab, r);
       double expo =
           c[0] + c[1] * tinv + c[2] * tm13 + c[3] * t13 + c[4] * T + c[5] * t53 + c[6] * lnT;
       if constexpr (SCR) expo += nt.screen[r] * G;
@@ -778,7 +805,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           fG = sqrt(frho * fS) / (T * sqrt(T));
         }
         for (int r = fi; r < R; r += FL) {
-          const double *c = s_rtab + 8 * (size_t)r;
+          const Coef c = coef_of(s_rtab, r);
           double expo =
               c[0] + c[1] * tinv + c[2] * tm13 + c[3] * t13 + c[4] * T + c[5] * t53 + c[6] * lnT;
           double dl = -c[1] * tinv * tinv - (1.0 / 3.0) * c[2] * tm13 * tinv +
