@@ -777,15 +777,21 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
       const bool frow = fi < MROWS;
       double *uacc = fM + (size_t)MROWS * MS;  // screening: sum_r W_ir h_r R_r
-      if (frow) {
-        if constexpr (SCR) uacc[fi] = 0.0;
-        double *mr = fM + fi * MS;
-        if constexpr (SH::COMPACT) {
+      // the identity
+      if constexpr (SH::COMPACT) {
+        if (frow) {
+          if constexpr (SCR) uacc[fi] = 0.0;
+          double *mr = fM + fi * MS;
           for (int j = 0; j < MROWS; ++j) mr[j] = (fi == j) ? 1.0 : 0.0;
-        } else {
-#pragma unroll
-          for (int j = 0; j < NP; ++j) mr[j] = (fi == j) ? 1.0 : 0.0;
         }
+      } else {
+        // the slot's FL lanes zero its matrix together (consecutive
+        // addresses, constant offsets), then each row lane sets its diagonal
+#pragma unroll
+        for (int i = 0; i < NP * (NP + 1); i += FL) fM[i + fi] = 0.0;
+        wave_lds_sync();
+        if constexpr (SCR) uacc[fi] = 0.0;
+        fM[fi * MS + fi] = 1.0;
       }
       wave_lds_sync();
       // Rates at y_J for the reactions r = fi, fi+FL, ...; every Jacobian term
