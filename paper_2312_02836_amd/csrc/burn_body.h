@@ -44,6 +44,7 @@ constexpr double kMinFactor = 0.2;
 constexpr double kMaxFactor = 10.0;
 constexpr double kNewtonTol = 0.03;
 constexpr int kNewtonMaxIt = 4;
+constexpr int kMaxDefer = 16;  // iterations an LU request may wait for company
 
 // per-cell phases: the two initial-step RHS, Newton iterations, finished
 // (outputs pending), waiting for a cell, no more cells
@@ -565,7 +566,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   int phase = PH_LOAD;
   int status = 0, write_state = 0;
   int k = 1, n_eq = 0, jac_cur = 0, lu_ok = 0, it = 0, need_attempt = 0, new_step = 0;
-  int fresh_newton = 0, first_jac = 0;
+  int fresh_newton = 0, first_jac = 0, defer_it = 0;
   double t = 0.0, h = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, err = 0.0, h0 = 0.0, d1 = 0.0;
 
   // outputs of the group's cell: state (if integration started), status and
@@ -725,7 +726,24 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     }
 
     // ---------------- B: LU pass for the cells that need one ----------------
-    const int want = (phase == PH_NEWTON && fresh_newton && !lu_ok);
+    // A pass costs the same whatever number of its slots are used.  When the
+    // wave can factor several cells in one pass, LU requests wait (up to
+    // kMaxDefer iterations) until every slot would be used, or every cell
+    // that still has work wants one.  A waiting cell does nothing in those
+    // iterations (no RHS, no Newton), so its own computation, and its
+    // results, are unchanged.
+    int want = (phase == PH_NEWTON && fresh_newton && !lu_ok);
+    int defer = 0;
+    if constexpr (FC >= 2 && CPW >= 2) {
+      const unsigned long long wm = __ballot(want && q == 0);
+      const unsigned long long expired = __ballot(want && q == 0 && defer_it >= kMaxDefer);
+      const int busy =
+          __popcll(__ballot((phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && q == 0));
+      const int target = busy < FC ? busy : FC;
+      if (want && __popcll(wm) < target && !expired) defer = 1;
+      defer_it = defer ? defer_it + 1 : 0;
+      if (defer) want = 0;
+    }
     int sing = 0;
     unsigned long long wmask = __ballot(want && q == 0);
     while (wmask) {
@@ -1062,10 +1080,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     double pend = 0.0;
     // a singular Newton matrix is a failed Newton attempt (no RHS needed)
     int nfail = (want && phase == PH_NEWTON && sing) ? 1 : 0;
-    fresh_newton = 0;
+    if (!defer) fresh_newton = 0;
 
     // ---------------- C: right-hand side ----------------
-    const int do_rhs = (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail;
+    const int do_rhs = (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail && !defer;
     int okf = 1;
     if (do_rhs) {
       okf = rhs();
