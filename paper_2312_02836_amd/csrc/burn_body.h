@@ -395,6 +395,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 
   // ---- per-lane state (group layout)
   double LU[S][NP];  // factor rows held at positions s*L+q
+  // register factorization: row q of the cell's J(y_J), kept between passes
+  double Jr[REG_LU ? NP : 1];
+  int jr_ok = 0;  // Jr holds J(y_J)
   double dinv[S];    // 1 / U_pp of those rows
   int ridx[S];       // natural index of those rows
   double yp[S], psi[S], isc[S], dd[S], yv[S], yJ[S], F[S];
@@ -412,6 +415,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       if (s * L + q < nt.N) wsqv[s] = nt.wsq[s * L + q];
     }
   }
+#pragma unroll
+  for (int j = 0; j < (REG_LU ? NP : 1); ++j) Jr[j] = 0.0;
   int cnt[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) cnt[c] = 0;
@@ -795,7 +800,15 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
       const bool frow = fi < MROWS;
       double *uacc = fM + (size_t)MROWS * MS;  // screening: sum_r W_ir h_r R_r
-      // the identity
+      // With register factorization J(y_J) is kept in the lanes' Jr registers
+      // and assembled (into LDS, unscaled, from a zero matrix) only when it
+      // was refreshed; otherwise the pass builds I - cJ from Jr.  Without it,
+      // every pass assembles I - cJ itself from the identity.
+      bool asm_j = true;
+      if constexpr (REG_LU) asm_j = fsel >= 0 && !jr_ok;
+      const bool any_asm = !REG_LU || __ballot(asm_j) != 0;
+      int jbad = 0;
+      if (any_asm) {
       if constexpr (SH::COMPACT) {
         if (frow) {
           if constexpr (SCR) uacc[fi] = 0.0;
@@ -809,15 +822,16 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         for (int i = 0; i < NP * (NP + 1); i += FL) fM[i + fi] = 0.0;
         wave_lds_sync();
         if constexpr (SCR) uacc[fi] = 0.0;
-        fM[fi * MS + fi] = 1.0;
+        if constexpr (!REG_LU) fM[fi * MS + fi] = 1.0;
       }
       wave_lds_sync();
+      // the scale of the assembled terms: -c into I - cJ, or 1 into J
+      const double ascale = REG_LU ? 1.0 : -fcc;
       // Rates at y_J for the reactions r = fi, fi+FL, ...; every Jacobian term
       // W(i, r) dR_r/dy_j (W = nu for a species row, q/c_v for the temperature
       // row) is added, times -c, into the Newton matrix I - cJ.
-      int jbad = 0;
       double fG = 0.0, fS = 1.0;
-      if (fsel >= 0) {
+      if (fsel >= 0 && asm_j) {
         const double T = fy[N];
         const double t13 = cbrt(T);
         const double tm13 = 1.0 / t13;
@@ -869,7 +883,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             const int col = (aa < 3) ? sp[aa] : N;
             if (col >= 0) {
               if (!isfinite(g[aa])) jbad = 1;
-              const double val = -fcc * g[aa];
+              const double val = ascale * g[aa];
 #pragma unroll
               for (int e = 0; e < 6; ++e) {
                 if (e < r0.x)
@@ -898,13 +912,14 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       if constexpr (SCR) {
         // rank-one composition term: -c u_i dG/dY_j, dG/dY_j = G A_j^2 / (2 S)
         wave_lds_sync();
-        if (fsel >= 0 && fi < n) {
-          const double ui = -fcc * uacc[fi] * fG / (2.0 * fS);
+        if (fsel >= 0 && asm_j && fi < n) {
+          const double ui = ascale * uacc[fi] * fG / (2.0 * fS);
           double *mr = fM + fi * MS;
           for (int j = 0; j < N; ++j) mr[j] += ui * nt.wsq[j];
           if (!isfinite(ui)) jbad = 1;
         }
       }
+      }  // any_asm
       jbad = gor<FL>(jbad);
       wave_lds_sync();
       // (c) LU with partial pivoting, one row per lane.  Rows are not moved:
@@ -918,11 +933,17 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         // cell); per pivot the pivot row's remaining entries go through the
         // y_J area of the slot, which is free once the Jacobian is built.
         const bool mine = fsel >= 0;
+        static_assert(!SH::COMPACT, "register factorization keeps all NP rows");
         if (mine) {
-          const double *mr = fM + (frow ? fi : 0) * MS;
+          if (asm_j) {
+            const double *mr = fM + fi * MS;
 #pragma unroll
-          for (int j = 0; j < NP; ++j)
-            LU[0][j] = (frow && (!SH::COMPACT || j < n)) ? mr[j] : 0.0;
+            for (int j = 0; j < NP; ++j) Jr[j] = mr[j];
+            jr_ok = 1;
+          }
+          // I - cJ
+#pragma unroll
+          for (int j = 0; j < NP; ++j) LU[0][j] = (fi == j ? 1.0 : 0.0) - fcc * Jr[j];
         }
         wave_lds_sync();
         Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
@@ -1142,6 +1163,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         }
         cnt[CNT_JAC]++;
         jac_cur = 1;
+        jr_ok = 0;
         first_jac = 1;
         lu_ok = 0;
         k = 1;
@@ -1297,6 +1319,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         }
         cnt[CNT_JAC]++;
         jac_cur = 1;
+        jr_ok = 0;
         lu_ok = 0;
         it = 0;
         fresh_newton = 1;
