@@ -92,7 +92,9 @@ __device__ __forceinline__ double rate_and_slots(const Tabs &tb, int r, const TP
                       c[5] * tp.t53 + c[6] * tp.lnT;
   const int *sp = tb.rsp + 4 * r;
   double pre = exp(expo) * tb.emult[r] * c[7];
-  for (int i = 1; i < sp[3]; ++i) pre *= rho;
+  // rho^(n_r - 1) for n_r <= 3 reactants
+  if (sp[3] >= 2) pre *= rho;
+  if (sp[3] >= 3) pre *= rho;
   const double ya = sp[0] >= 0 ? ybuf[sp[0]] : 1.0;
   const double yb = sp[1] >= 0 ? ybuf[sp[1]] : 1.0;
   const double yc = sp[2] >= 0 ? ybuf[sp[2]] : 1.0;

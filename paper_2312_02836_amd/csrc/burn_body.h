@@ -445,16 +445,19 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       double dcol[KMAX + 1];
 #pragma unroll
       for (int b = 0; b <= KMAX; ++b) dcol[b] = (b <= k) ? Dl[b * NP + i] : 0.0;
+      // rows b > k are zero in dcol, so their terms add exactly nothing; the
+      // node m = 0 reproduces D_0; entries aa <= k use only m <= aa <= k
       double v[KMAX + 1];
+      v[0] = dcol[0];
 #pragma unroll
-      for (int m = 0; m <= KMAX; ++m) {
+      for (int m = 1; m <= KMAX; ++m) {
         const double x = (double)m * rh;
         double rb = 1.0;
         double acc = dcol[0];
 #pragma unroll
         for (int b = 1; b <= KMAX; ++b) {
           rb *= ((double)(b - 1) - x) * (1.0 / (double)b);
-          if (b <= k) acc += rb * dcol[b];
+          acc += rb * dcol[b];
         }
         v[m] = acc;
       }
@@ -462,8 +465,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       for (int aa = 0; aa <= KMAX; ++aa) {
         double acc = 0.0;
 #pragma unroll
-        for (int m = 0; m <= aa; ++m)
-          if (m <= k) acc += u_of(m, aa) * v[m];
+        for (int m = 0; m <= aa; ++m) acc += u_of(m, aa) * v[m];
         if (aa <= k) Dl[aa * NP + i] = acc;
       }
     }
@@ -503,7 +505,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       if constexpr (SCR) expo += nt.screen[r] * G;
       const int *sp = s_rsp + 4 * r;
       double v = exp(expo) * s_emult[r] * c[7];
-      for (int i = 1; i < sp[3]; ++i) v *= rho;
+      // rho^(n_r - 1) for n_r <= 3 reactants
+      if (sp[3] >= 2) v *= rho;
+      if (sp[3] >= 3) v *= rho;
       if (sp[0] >= 0) v *= ybuf[sp[0]];
       if (sp[1] >= 0) v *= ybuf[sp[1]];
       if (sp[2] >= 0) v *= ybuf[sp[2]];
@@ -857,7 +861,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           }
           const int *sp = s_rsp + 4 * r;
           double pre = exp(expo) * s_emult[r] * c[7];
-          for (int i = 1; i < sp[3]; ++i) pre *= frho;
+          // rho^(n_r - 1) for n_r <= 3 reactants
+          if (sp[3] >= 2) pre *= frho;
+          if (sp[3] >= 3) pre *= frho;
           const double ya = sp[0] >= 0 ? fy[sp[0]] : 1.0;
           const double yb = sp[1] >= 0 ? fy[sp[1]] : 1.0;
           const double yc = sp[2] >= 0 ? fy[sp[2]] : 1.0;
