@@ -556,17 +556,20 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           if (comp(s) > K) b[s] -= LU[s][K] * xk;
       }
     });
-    // back substitution with the upper factor
+    // back substitution with the upper factor: at step K component K is
+    // final, x_K = b_K / U_KK goes to the components above it; each lane
+    // scales its own components once at the end (the same product)
     Unroll<NP>::run([&]<int KK>() __attribute__((always_inline)) {
       constexpr int K = NP - 1 - KK;
       if (K < n) {
         const double xk = gbcast<L, K % L>(b[K / L] * dinv[K / L]);
-        if (q == K % L) b[K / L] = xk;
 #pragma unroll
         for (int s = 0; s <= K / L; ++s)
           if (comp(s) < K) b[s] -= LU[s][K] * xk;
       }
     });
+#pragma unroll
+    for (int s = 0; s < S; ++s) b[s] = b[s] * dinv[s];
     wave_lds_sync();
   };
 
