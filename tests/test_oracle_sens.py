@@ -126,3 +126,50 @@ def test_vjp_is_the_contraction_of_S(oracle):
     for c in range(8):
         ref = gY[:, c] @ S[c, :spec.n_species] + gE[c] * spec.c_v * S[c, spec.n_species]
         assert np.allclose(g[:, c], ref, rtol=1e-14, atol=0)
+
+
+def test_sens_matches_continuous_sensitivities(oracle):
+    """The discrete sensitivities at tight tolerance (rtol 1e-8) against the
+    continuous ones of the 13-species / 30-reaction network, computed by the
+    staggered direct method: scipy's Radau for y (rtol 1e-12, dense output),
+    then for every multiplier the linear system s' = J(y(t)) s + df/dp_r
+    (rtol 1e-10).  df/dp_r = W_r R_r is a central difference of the oracle's
+    RHS in p_r (f is linear in e^{p_r}).  The discrete map converges to the
+    continuous one as rtol -> 0: the difference is O(rtol) of the largest
+    sensitivity (about 1e-7 of it here)."""
+    from scipy.integrate import solve_ivp
+    cfg = synth.config(2, n_cells=16)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    net = oracle.OracleNet(spec)
+    R, n = spec.n_reactions, spec.n
+    idx = np.array([9, 3])
+    sub = cells.subset(idx)
+    Yd, Td, st, cnt, S, unc = oracle.sens(net, sub, cfg.t_end, 1e-8, 1e-12)
+    assert np.all(st == 0)
+    hp = 1e-6
+    for c in range(len(idx)):
+        rho = sub.rho[c]
+        y0 = np.concatenate([sub.Y[:, c], [sub.T[c]]])
+        sy = solve_ivp(lambda t, y: oracle.rhs(net, rho, y), (0.0, cfg.t_end), y0,
+                       method="Radau", rtol=1e-12, atol=1e-16,
+                       jac=lambda t, y: oracle.jac(net, rho, y), dense_output=True)
+        assert sy.success
+        Sc = np.zeros((n, R))
+        for r in range(R):
+            e = np.zeros(R)
+            e[r] = hp
+
+            def g(t, s, e=e):
+                y = sy.sol(t)
+                fp = (oracle.rhs(net, rho, y, log_mult=e) - oracle.rhs(net, rho, y, log_mult=-e)) / (2 * hp)
+                return oracle.jac(net, rho, y) @ s + fp
+
+            ss = solve_ivp(g, (0.0, cfg.t_end), np.zeros(n), method="Radau", rtol=1e-10, atol=1e-14,
+                           jac=lambda t, s: oracle.jac(net, rho, sy.sol(t)))
+            assert ss.success
+            Sc[:, r] = ss.y[:, -1]
+        big = np.abs(Sc).max()
+        d = np.abs(S[c] - Sc)
+        print(f"cell {idx[c]}: max |S_discrete - S_continuous| = {d.max() / big:.2e} of max |S|")
+        assert d.max() <= 1e-5 * big
+        assert np.all(d <= 1e-4 * np.abs(Sc).max(axis=0, keepdims=True) + 1e-6 * big)
