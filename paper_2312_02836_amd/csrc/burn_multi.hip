@@ -27,7 +27,26 @@ hipError_t launch_plain_p2(const BurnArgs &a, int L, int S, int block_waves, hip
 
 namespace {
 
-template <int W>
+// Shape index sh of the W-waves-per-SIMD set, fixed at compile time.
+template <int W, int SH>
+__device__ __forceinline__ void run_shape(const BurnArgs &a, const Tabs &tb, double *wb,
+                                          unsigned long long *qj) {
+  if constexpr (W == 2) {
+    if constexpr (SH == 0) run_cells<8, 1, true>(a, tb, wb, 0, qj);
+    else if constexpr (SH == 1) run_cells<16, 1, true>(a, tb, wb, 0, qj);
+    else if constexpr (SH == 2) run_cells<32, 1, true>(a, tb, wb, 0, qj);
+    else run_cells<64, 1, true>(a, tb, wb, 0, qj);
+  } else {
+    if constexpr (SH == 0) run_cells<4, 4, true>(a, tb, wb, 0, qj);
+    else if constexpr (SH == 1) run_cells<16, 2, true>(a, tb, wb, 0, qj);
+    else if constexpr (SH == 2) run_cells<32, 1, true>(a, tb, wb, 0, qj);
+    else run_cells<64, 1, true>(a, tb, wb, 0, qj);
+  }
+}
+
+// ONE >= 0: every item has shape ONE (one burn body, the registers of that
+// shape alone); ONE < 0: the shape is chosen per item.
+template <int W, int ONE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
 burn_multi_kernel(MultiArgs m) {
   extern __shared__ double smem[];
@@ -47,19 +66,14 @@ burn_multi_kernel(MultiArgs m) {
     if (skip) continue;
     const Tabs tb = tabs_at(smem, a.net.R);
     unsigned long long *qj = m.queue + j;
-    if constexpr (W == 2) {
-      switch (m.shape[j]) {
-        case 0: run_cells<8, 1, true>(a, tb, wb, 0, qj); break;
-        case 1: run_cells<16, 1, true>(a, tb, wb, 0, qj); break;
-        case 2: run_cells<32, 1, true>(a, tb, wb, 0, qj); break;
-        default: run_cells<64, 1, true>(a, tb, wb, 0, qj); break;
-      }
+    if constexpr (ONE >= 0) {
+      run_shape<W, ONE>(a, tb, wb, qj);
     } else {
       switch (m.shape[j]) {
-        case 0: run_cells<4, 4, true>(a, tb, wb, 0, qj); break;
-        case 1: run_cells<16, 2, true>(a, tb, wb, 0, qj); break;
-        case 2: run_cells<32, 1, true>(a, tb, wb, 0, qj); break;
-        default: run_cells<64, 1, true>(a, tb, wb, 0, qj); break;
+        case 0: run_shape<W, 0>(a, tb, wb, qj); break;
+        case 1: run_shape<W, 1>(a, tb, wb, qj); break;
+        case 2: run_shape<W, 2>(a, tb, wb, qj); break;
+        default: run_shape<W, 3>(a, tb, wb, qj); break;
       }
     }
   }
@@ -111,12 +125,29 @@ hipError_t launch_plain(const BurnArgs &a, int L, int S, int block_waves, hipStr
 
 hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream) {
   const size_t lds = 8 * (m.tab_doubles + (size_t)m.block_waves * m.wave_doubles);
-  if (W == 2)
-    hipLaunchKernelGGL((burn_multi_kernel<2>), dim3((unsigned)grid), dim3(64 * m.block_waves),
-                       lds, stream, m);
-  else
-    hipLaunchKernelGGL((burn_multi_kernel<1>), dim3((unsigned)grid), dim3(64 * m.block_waves),
-                       lds, stream, m);
+  const dim3 g((unsigned)grid), blk(64 * m.block_waves);
+  int one = m.n_items > 0 ? m.shape[0] : -1;
+  for (int j = 1; j < m.n_items; ++j)
+    if (m.shape[j] != one) one = -1;
+#define BN_MULTI(w, o) hipLaunchKernelGGL((burn_multi_kernel<w, o>), g, blk, lds, stream, m)
+  if (W == 2) {
+    switch (one) {
+      case 0: BN_MULTI(2, 0); break;
+      case 1: BN_MULTI(2, 1); break;
+      case 2: BN_MULTI(2, 2); break;
+      case 3: BN_MULTI(2, 3); break;
+      default: BN_MULTI(2, -1); break;
+    }
+  } else {
+    switch (one) {
+      case 0: BN_MULTI(1, 0); break;
+      case 1: BN_MULTI(1, 1); break;
+      case 2: BN_MULTI(1, 2); break;
+      case 3: BN_MULTI(1, 3); break;
+      default: BN_MULTI(1, -1); break;
+    }
+  }
+#undef BN_MULTI
   return hipGetLastError();
 }
 
