@@ -258,7 +258,22 @@ adjoint_kernel(AdjArgs a) {
       if (own && pos > K) {
         const double l = Mrow[K] * rinv;
         Mrow[K] = l;
-        for (int j = K + 1; j < n; ++j) Mrow[j] -= l * P[j];
+        // whole chunks of 4 columns (loads issued together), then the rest
+        int j0 = K + 1;
+        for (; j0 + 4 <= n; j0 += 4) {
+          double x[4], y[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            x[u] = Mrow[j0 + u];
+            y[u] = P[j0 + u];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            x[u] -= l * y[u];
+            Mrow[j0 + u] = x[u];
+          }
+        }
+        for (; j0 < n; ++j0) Mrow[j0] -= l * P[j0];
       }
       wave_lds_sync();
     }

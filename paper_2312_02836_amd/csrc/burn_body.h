@@ -278,7 +278,7 @@ struct Shape {
   static constexpr int CPW = 64 / L;
   static constexpr int FL = NP;       // factor lanes per cell (one row each)
   static constexpr int FC = 64 / NP;  // cells per factorization pass
-  static constexpr int ECH = 4;  // elimination columns per LDS batch
+  static constexpr int ECH = NP >= 64 ? 8 : 4;  // elimination columns per LDS batch
   static_assert(NP == 4 || NP == 8 || NP == 16 || NP == 32 || NP == 64, "NP must be a power of 2");
   // Per-cell strides.  A wave's LDS access is served half a wave (32 lanes)
   // at a time; the 32/L cells of a half-wave each touch 2L consecutive banks
@@ -1034,25 +1034,24 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           if (frow && pos > K) {
             const double l = mk * rinv;
             Mrow[K] = l;
-            // chunks of ECH columns: all loads of a chunk are issued before the
-            // first use, so the LDS latency is paid once per chunk
-            for (int j0 = K + 1; j0 < n; j0 += ECH) {
+            // whole chunks of ECH columns (all loads of a chunk are issued
+            // before the first use, so the LDS latency is paid once per
+            // chunk), then the remaining columns one by one
+            int j0 = K + 1;
+            for (; j0 + ECH <= n; j0 += ECH) {
               double a[ECH], b[ECH];
 #pragma unroll
               for (int u = 0; u < ECH; ++u) {
-                if (j0 + u < n) {
-                  a[u] = Mrow[j0 + u];
-                  b[u] = P[j0 + u];
-                }
+                a[u] = Mrow[j0 + u];
+                b[u] = P[j0 + u];
               }
 #pragma unroll
               for (int u = 0; u < ECH; ++u) {
-                if (j0 + u < n) {
-                  a[u] -= l * b[u];
-                  Mrow[j0 + u] = a[u];
-                }
+                a[u] -= l * b[u];
+                Mrow[j0 + u] = a[u];
               }
             }
+            for (; j0 < n; ++j0) Mrow[j0] -= l * P[j0];
           }
           wave_lds_sync();
         }
