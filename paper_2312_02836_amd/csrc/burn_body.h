@@ -547,9 +547,12 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     wave_lds_sync();
 #pragma unroll
     for (int s = 0; s < S; ++s) b[s] = ybuf[ridx[s]];
-    // forward substitution with the unit lower factor
+    // forward substitution with the unit lower factor.  Positions K >= n
+    // are padding (zero right-hand side, zero factor columns, unit
+    // diagonal): with all NP rows stored they change nothing, so only the
+    // compact layout skips them.
     Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
-      if (K < n) {
+      if (!SH::COMPACT || K < n) {
         const double xk = gbcast<L, K % L>(b[K / L]);
 #pragma unroll
         for (int s = K / L; s < S; ++s)
@@ -561,7 +564,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     // scales its own components once at the end (the same product)
     Unroll<NP>::run([&]<int KK>() __attribute__((always_inline)) {
       constexpr int K = NP - 1 - KK;
-      if (K < n) {
+      if (!SH::COMPACT || K < n) {
         const double xk = gbcast<L, K % L>(b[K / L] * dinv[K / L]);
 #pragma unroll
         for (int s = 0; s <= K / L; ++s)
