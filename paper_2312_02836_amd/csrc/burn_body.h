@@ -22,8 +22,12 @@
 //    needs one.  The cells that need a factorization are therefore batched
 //    into a wave-wide pass in which every cell gets FL = NP lanes, one matrix
 //    row per lane: the Newton matrix is accumulated in LDS from the
-//    reaction-parallel Jacobian terms, the LU runs in LDS with row-position
+//    reaction-parallel Jacobian terms, the LU runs with row-position
 //    tracking (no data swaps), and the factors go back to the owning group.
+//    One-slot shapes of up to 16 lanes eliminate in the owners' registers
+//    and keep J between passes; a lone request waits a few iterations for
+//    other cells to need an LU too, since a pass costs the same for one cell
+//    as for all.
 //  * Control.  Each loop iteration does, per cell: (0) output of a finished
 //    cell and intake of the next, (A) step-attempt setup, (B) the wave-wide
 //    factorization pass, (C) one right-hand side, (D) the Newton /
