@@ -77,10 +77,10 @@ __device__ __forceinline__ TPow tpow(double T) {
   TPow p;
   p.T = T;
   p.t13 = cbrt(T);
-  p.tm13 = 1.0 / p.t13;
+  p.tinv = 1.0 / T;
+  p.tm13 = (p.t13 * p.t13) * p.tinv;  // T^(-1/3) = T^(2/3) / T
   p.t53 = T * p.t13 * p.t13;
   p.lnT = bn_log(T);
-  p.tinv = 1.0 / T;
   return p;
 }
 

@@ -490,10 +490,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     wave_lds_sync();
     const double T = ybuf[N];
     const double t13 = cbrt(T);
-    const double tm13 = 1.0 / t13;
+    const double tinv = 1.0 / T;
+    const double tm13 = (t13 * t13) * tinv;  // T^(-1/3) = T^(2/3) / T
     const double t53 = T * t13 * t13;
     const double lnT = bn_log(T);
-    const double tinv = 1.0 / T;
     double G = 0.0;
     if constexpr (SCR) {
       double part = 0.0;
@@ -848,10 +848,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       if (fsel >= 0 && asm_j) {
         const double T = fy[N];
         const double t13 = cbrt(T);
-        const double tm13 = 1.0 / t13;
+        const double tinv = 1.0 / T;
+        const double tm13 = (t13 * t13) * tinv;  // T^(-1/3) = T^(2/3) / T
         const double t53 = T * t13 * t13;
         const double lnT = bn_log(T);
-        const double tinv = 1.0 / T;
         if constexpr (SCR) {
           for (int j = 0; j < N; ++j) fS += nt.wsq[j] * fy[j];
           fG = sqrt(frho * fS) / (T * sqrt(T));
