@@ -586,6 +586,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   int status = 0, write_state = 0;
   int k = 1, n_eq = 0, jac_cur = 0, lu_ok = 0, it = 0, need_attempt = 0, new_step = 0;
   int fresh_newton = 0, first_jac = 0, defer_it = 0;
+  int f_pre = 0, okf_pre = 1;  // F already holds f(predictor), computed while waiting
   double t = 0.0, h = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, err = 0.0, h0 = 0.0, d1 = 0.0;
 
   // outputs of the group's cell: state (if integration started), status and
@@ -624,6 +625,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     rho = grho[cell];
     status = 0;
     write_state = 0;
+    f_pre = 0;
     k = 1;
     n_eq = jac_cur = lu_ok = it = need_attempt = new_step = fresh_newton = first_jac = 0;
     t = h = t_new = cc = dprev = err = h0 = d1 = 0.0;
@@ -1119,12 +1121,27 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     if (!defer) fresh_newton = 0;
 
     // ---------------- C: right-hand side ----------------
-    const int do_rhs = (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail && !defer;
+    // A cell waiting for its LU already evaluates the first Newton RHS, at
+    // the predictor (which the wait does not change), and uses it once the
+    // factors are there.
+    if (nfail) f_pre = 0;
+    const int active = (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail;
+    const int need_f = active && !f_pre;
     int okf = 1;
-    if (do_rhs) {
+    if (need_f) {
       okf = rhs();
       cnt[CNT_RHS]++;
     }
+    if (defer) {
+      if (need_f) {
+        f_pre = 1;
+        okf_pre = okf;
+      }
+    } else if (f_pre) {
+      okf = okf_pre;
+      f_pre = 0;
+    }
+    const int do_rhs = active && !defer;  // the right-hand side is used now
 
     // ---------------- D: what the new right-hand side is used for ----------------
     if (do_rhs) {
