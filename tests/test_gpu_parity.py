@@ -160,3 +160,26 @@ def test_empty_and_determinism(gpu, oracle):
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[3], b[3])
     net.close()
+
+
+def test_cell_results_independent_of_neighbours(gpu, oracle):
+    """A cell's burn does not depend on which cells share its wave (LU
+    requests wait for each other, factorization passes are shared): the same
+    cells in a permuted order, and in the persistent kernel, give bitwise the
+    same per-cell results and counters."""
+    import torch
+    cfg = synth.config(2, n_cells=1024)
+    net = gpu.Network(cfg.networks[0])
+    c = cfg.cells[0]
+    perm = np.random.default_rng(5).permutation(c.n_cells)
+    inv = np.argsort(perm)
+    cp = c.subset(perm)
+    a = [x.cpu().numpy() for x in gpu.burn(net, c.Y, c.rho, c.T, cfg.t_end)]
+    b = [x.cpu().numpy() for x in gpu.burn(net, cp.Y, cp.rho, cp.T, cfg.t_end)]
+    m = [x.cpu().numpy() for x in gpu.burn_multi([(net, cp.Y, cp.rho, cp.T)], cfg.t_end)[0]]
+    torch.cuda.synchronize()
+    for x, y, z in zip(a, b, m):
+        yb = y[..., inv]
+        zb = z[..., inv]
+        assert np.array_equal(x, yb) and np.array_equal(x, zb)
+    net.close()
