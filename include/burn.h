@@ -266,7 +266,9 @@ size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells
  *   status      DEVICE [n_cells]     BN_CELL_* (required: the backward call
  *                                    reads it)
  *   counters    DEVICE [BN_N_COUNTERS][n_cells] or NULL (recording run)
- *   replay_iters DEVICE [n_cells] or NULL  Newton iterations of the replay
+ *   replay_iters DEVICE [2][n_cells] or NULL  per cell, the replay's Newton
+ *                                    iterations (row 0) and Newton-matrix
+ *                                    factorizations (row 1)
  * A cell that fails keeps the recording run's last accepted state. */
 int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const double *state0,
                                const double *rho, const double *T0, double dt, double rtol,

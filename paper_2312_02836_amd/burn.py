@@ -270,7 +270,8 @@ class AdjointRun:
         self.E = torch.empty_like(self.T0)
         self.status = torch.empty(self.C, dtype=torch.int32, device=device)
         self.counters = torch.empty((8, self.C), dtype=torch.int32, device=device)
-        self.replay_iters = torch.empty(self.C, dtype=torch.int32, device=device)
+        # the replay's Newton iterations [0] and factorizations [1] per cell
+        self.replay_iters = torch.empty((2, self.C), dtype=torch.int32, device=device)
         self.device = device
 
     def _stream(self):

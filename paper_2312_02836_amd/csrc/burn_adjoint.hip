@@ -9,7 +9,7 @@
 // order k_n), plus the initial step size.  The replay then takes, per step,
 //   D <- rescale(D, k_n, rho_n); y0 = sum_{j<=k} D_j;
 //   psi = sum_{j=1..k} gamma_j D_j / gamma_k;  c = h_n / gamma_k;
-//   d solves d + psi - c f(y0 + d; p) = 0 exactly (full Newton to 1e-10);
+//   d solves d + psi - c f(y0 + d; p) = 0 exactly (Newton to 1e-10);
 //   D_{k+1} = d; D_j += D_{j+1} (j = k..0),
 // starting from D_0 = y(0), D_1 = h_init f(y(0)), and y_end = D_0 (the
 // integrator's row D_{k+2} only feeds error estimates, i.e. the frozen
@@ -36,7 +36,8 @@ namespace bn {
 namespace {
 
 constexpr int CK = 16;          // accepted steps per checkpoint segment
-constexpr int ADJ_MAXIT = 8;    // full-Newton iterations of the exact corrector
+constexpr int ADJ_MAXIT = 12;   // iterations of the exact corrector
+constexpr double kChordRate = 0.1;  // slower contraction: a new Newton matrix
 constexpr double ADJ_TOL = 1e-10;
 constexpr int GR = 4;           // reactions per lane in the gradient (R <= 256)
 
@@ -171,7 +172,7 @@ adjoint_kernel(AdjArgs a) {
     } else {
       if (lane == 0) {
         a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
-        if (a.iters) a.iters[cell] = 0;
+        if (a.iters) a.iters[cell] = a.iters[C + cell] = 0;
       }
     }
     return;
@@ -364,8 +365,12 @@ adjoint_kernel(AdjArgs a) {
   };
 
   // the replay of one accepted step; returns the corrected state in y_new
-  // (this lane's component); 0 on a non-finite or singular corrector
-  int n_it = 0;  // Newton iterations of the replay
+  // (this lane's component); 0 on a non-finite or singular corrector.  The
+  // corrector equation is solved to ADJ_TOL; the iteration keeps the Newton
+  // matrix of the predictor while the increments shrink at least
+  // kChordRate-fold per iteration and takes a new one (a Newton step) when
+  // they do not, so its solution is the exact corrector either way.
+  int n_it = 0, n_lu = 0;  // Newton iterations and factorizations of the replay
   auto replay_step = [&](int m, double &y_new) -> int {
     const int k = so[m];
     const double hstep = sh[m], ratio = sr[m];
@@ -384,17 +389,20 @@ adjoint_kernel(AdjArgs a) {
     const double psi = sb / gk;
     const double isc = 1.0 / (a.atol + a.rtol * fabs(ypred));
     const double c = hstep / gk;
-    double d = 0.0, y = ypred;
-    int ok = 1;
+    double d = 0.0, y = ypred, dprev = 0.0;
+    int ok = 1, fresh = 1;
     for (int it = 0; it < ADJ_MAXIT; ++it) {
       ++n_it;
       if (own) ybuf[lane] = y;
       double F;
-      ok = eval_f_m(c, true, true, F);
+      ok = eval_f_m(c, true, fresh != 0, F);
       if (!ok) break;
-      if (!factor()) {
-        ok = 0;
-        break;
+      if (fresh) {
+        ++n_lu;
+        if (!factor()) {
+          ok = 0;
+          break;
+        }
       }
       const double dy = solve(c * F - psi - d);
       const double dn = wrms(dy, isc);
@@ -405,6 +413,8 @@ adjoint_kernel(AdjArgs a) {
       y += dy;
       d += dy;
       if (dn <= ADJ_TOL) break;
+      fresh = it > 0 && dn > kChordRate * dprev;
+      dprev = dn;
     }
     y_new = y;
     // history update (row k+2 of the production integrator only feeds its
@@ -443,7 +453,10 @@ adjoint_kernel(AdjArgs a) {
       }
       ok = replay_step(m, y_new);
     }
-    if (lane == 0 && a.iters) a.iters[cell] = n_it;
+    if (lane == 0 && a.iters) {
+      a.iters[cell] = n_it;
+      a.iters[C + cell] = n_lu;
+    }
     if (!ok) {
       if (lane == 0) a.status[cell] = ST_NONFINITE;
       return;

@@ -107,7 +107,8 @@ struct AdjArgs {
   const double *gY, *gE;        // cotangents (backward)
   double *grad;                 // [R][n_cells] (backward)
   int32_t *status;              // [n_cells] (forward: read and updated; backward: read)
-  int32_t *iters;               // [n_cells] or nullptr: replay Newton iterations (forward)
+  int32_t *iters;               // [2][n_cells] or nullptr: replay Newton iterations and
+                                // factorizations (forward)
   double *sched;                // schedule blocks (see BurnArgs)
   int64_t sched_stride;
   int sched_cap;

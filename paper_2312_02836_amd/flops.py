@@ -69,12 +69,13 @@ def adjoint_cell_flops(spec, counters: np.ndarray, replay_iters: np.ndarray) -> 
     """Per-cell algorithmic operation count of one sensitivity run (recording
     burn, replay with exact correctors, checkpointed recomputation and the
     reverse sweep), from the recording run's counters [8, C] and the replay's
-    Newton iterations [C].
+    Newton iterations and factorizations [2, C].
 
       recording     cell_flops (the production burn)
-      replay        2 x iterations x (F_rhs + F_jac + F_lu + F_solve)  (the
-                    forward replay and the segment recomputation), plus per
-                    accepted step 2 x (rescale, predictor, update) = 2 x 174 n
+      replay        2 x (iterations x (F_rhs + F_solve) + factorizations x
+                    (F_jac + F_lu))  (the forward replay and the segment
+                    recomputation), plus per accepted step 2 x (rescale,
+                    predictor, update) = 2 x 174 n
       reverse       per accepted step: Newton matrix and factors at the
                     corrected state (F_jac + F_lu), the transposed solve
                     (2 n^2 - n), the per-reaction contraction with J^T and
@@ -82,11 +83,12 @@ def adjoint_cell_flops(spec, counters: np.ndarray, replay_iters: np.ndarray) -> 
                     history maps (60 n)
     """
     c = np.asarray(counters, dtype=np.int64)
-    it = np.asarray(replay_iters, dtype=np.int64)
+    ri = np.asarray(replay_iters, dtype=np.int64)
+    it, nf = ri[0], ri[1]
     n_steps = c[0]
     k = per_eval_costs(spec)
     n = spec.n
-    f_it = k["rhs"] + k["jac"] + k["lu"] + k["solve"]
+    f_replay = it * (k["rhs"] + k["solve"]) + nf * (k["jac"] + k["lu"])
     f_rev = 2 * k["jac"] + k["lu"] + (2 * n * n - n) + 60 * n + 2 * spec.n_reactions * 6
-    return (cell_flops(spec, counters) + 2 * it * f_it + n_steps * (2 * 174 * n + f_rev)
+    return (cell_flops(spec, counters) + 2 * f_replay + n_steps * (2 * 174 * n + f_rev)
             + k["rhs"] + k["jac"])
