@@ -91,14 +91,19 @@ __device__ __forceinline__ double rate_and_slots(const Tabs &tb, int r, const TP
   const Coef c = coef_of(tb.rtab, r);
   const double expo = c[0] + c[1] * tp.tinv + c[2] * tp.tm13 + c[3] * tp.t13 + c[4] * tp.T +
                       c[5] * tp.t53 + c[6] * tp.lnT;
-  const int *sp = tb.rsp + 4 * r;
+  const int4 spv = *reinterpret_cast<const int4 *>(tb.rsp + 4 * r);
+  const int sp[4] = {spv.x, spv.y, spv.z, spv.w};
+  // unconditional slot loads (an absent slot reads entry 0 and stands for 1)
+  const double fa = ybuf[sp[0] < 0 ? 0 : sp[0]];
+  const double fb = ybuf[sp[1] < 0 ? 0 : sp[1]];
+  const double fc = ybuf[sp[2] < 0 ? 0 : sp[2]];
   double pre = exp(expo) * tb.emult[r] * c[7];
   // rho^(n_r - 1) for n_r <= 3 reactants
   if (sp[3] >= 2) pre *= rho;
   if (sp[3] >= 3) pre *= rho;
-  const double ya = sp[0] >= 0 ? ybuf[sp[0]] : 1.0;
-  const double yb = sp[1] >= 0 ? ybuf[sp[1]] : 1.0;
-  const double yc = sp[2] >= 0 ? ybuf[sp[2]] : 1.0;
+  const double ya = sp[0] >= 0 ? fa : 1.0;
+  const double yb = sp[1] >= 0 ? fb : 1.0;
+  const double yc = sp[2] >= 0 ? fc : 1.0;
   double full = pre;
   if (sp[0] >= 0) full *= ya;
   if (sp[1] >= 0) full *= yb;
@@ -138,6 +143,7 @@ adjoint_kernel(AdjArgs a) {
   const Tabs tb = tabs_at(smem, a.net.R);
   const NetTables &nt = a.net;
   const int N = nt.N, R = nt.R, n = nt.n;
+  const int ne = nt.max_ent;  // entries per reaction, padded (ent_of)
   const int MS = n | 1;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -198,11 +204,14 @@ adjoint_kernel(AdjArgs a) {
       const double v = rate_and_slots(tb, r, tp, ybuf, rho, want_m, g);
       const int4 *ro = reinterpret_cast<const int4 *>(tb.rout + 8 * r);
       const int4 r0 = ro[0], r1 = ro[1];
-      const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
       if (want_f) {
         heat += tb.q[r] * v;
-        for (int e = 0; e < r0.x; ++e)
-          lds_add(&facc[ent[e] >> 8], (double)(signed char)(ent[e] & 0xff) * v);
+        Unroll<6>::run([&]<int E>() __attribute__((always_inline)) {
+          if (E < ne) {
+            const Ent en = ent_of<E>(r0, r1);
+            lds_add(&facc[en.sp], en.w * v);
+          }
+        });
       }
       if (want_m) {
         const int *sp = tb.rsp + 4 * r;
@@ -212,8 +221,12 @@ adjoint_kernel(AdjArgs a) {
           if (col < 0) continue;
           if (!isfinite(g[s])) bad = 1;
           const double val = -c * g[s];
-          for (int e = 0; e < r0.x; ++e)
-            lds_add(&M[(ent[e] >> 8) * MS + col], (double)(signed char)(ent[e] & 0xff) * val);
+          Unroll<6>::run([&]<int E>() __attribute__((always_inline)) {
+            if (E < ne) {
+              const Ent en = ent_of<E>(r0, r1);
+              lds_add(&M[en.sp * MS + col], en.w * val);
+            }
+          });
           lds_add(&M[N * MS + col], qc * val);
         }
       }

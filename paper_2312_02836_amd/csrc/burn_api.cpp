@@ -249,6 +249,7 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
     for (int r = 0; r < R; ++r) nu8[(size_t)i * R + r] = (signed char)nu_of(d, i, r);
   // per reaction: the species it changes and by how much (at most 6)
   std::vector<int> rout(8 * (size_t)R, 0);
+  int max_ent = 0;
   for (int r = 0; r < R; ++r) {
     int c = 0;
     for (int i = 0; i < N; ++i) {
@@ -256,6 +257,7 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
       if (v) rout[8 * r + 1 + c++] = (i << 8) | (v & 0xff);
     }
     rout[8 * r] = c;
+    if (c > max_ent) max_ent = c;
   }
 
   auto *net = new bn_network();
@@ -320,6 +322,7 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
   t.row_off = reinterpret_cast<const int *>(base + o_rowoff);
   t.row_r = reinterpret_cast<const int *>(base + o_rowr);
   t.nsl = nsl;
+  t.max_ent = max_ent;
   t.col_off = reinterpret_cast<const int *>(base + o_coloff);
   t.col_ent = reinterpret_cast<const int *>(base + o_colent);
   t.nu8 = reinterpret_cast<const signed char *>(base + o_nu8);

@@ -309,6 +309,36 @@ struct Tabs {
   const int *rsp, *rout;
 };
 
+// Entry e (0..5) of a reaction's species list (rout row ro0, ro1).  Past
+// the reaction's own count the list is padded, up to the network's largest
+// count, with coefficient-0 entries on its first listed species, so that all
+// lanes of a wave take the same number of entries without a branch per entry.
+// A padded entry adds w x = +-0 (it leaves the accumulator unchanged unless
+// that holds -0), or NaN when x is not finite; x is then a rate or a rate
+// derivative of the same reaction, and that reaction's heat term (q x) or the
+// caller's finiteness check already marks the evaluation as failed.
+struct Ent {
+  int sp;    // species
+  double w;  // nu_ir, or 0 for a padded entry
+};
+template <int E>
+__device__ __forceinline__ Ent ent_of(const int4 &ro0, const int4 &ro1) {
+  static_assert(E >= 0 && E < 6, "a reaction changes at most 6 species");
+  constexpr int kLane = E + 1;  // position in the row after the count
+  const int raw = kLane == 1   ? ro0.y
+                  : kLane == 2 ? ro0.z
+                  : kLane == 3 ? ro0.w
+                  : kLane == 4 ? ro1.x
+                  : kLane == 5 ? ro1.y
+                               : ro1.z;
+  const bool on = E < ro0.x;
+  const int e = on ? raw : ro0.y;
+  Ent r;
+  r.sp = e >> 8;
+  r.w = (double)(on ? (int)(signed char)(e & 0xff) : 0);
+  return r;
+}
+
 __device__ __forceinline__ Tabs tabs_at(double *smem, int R) {
   Tabs t;
   t.rtab = smem;
@@ -367,6 +397,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 
   const NetTables &nt = a.net;
   const int N = nt.N, R = nt.R;
+  const int ne = nt.max_ent;  // entries per reaction, padded (ent_of)
   int n = nt.n;  // re-derived opaquely in every iteration, like q
   const int MS = SH::ms(n);
   const int MROWS = SH::rows(n);
@@ -507,24 +538,29 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       double expo =
           c[0] + c[1] * tinv + c[2] * tm13 + c[3] * t13 + c[4] * T + c[5] * t53 + c[6] * lnT;
       if constexpr (SCR) expo += nt.screen[r] * G;
-      const int *sp = s_rsp + 4 * r;
+      // reactant slots: all loads issued unconditionally (an absent slot
+      // reads entry 0 and multiplies by 1), so they overlap the exponential
+      const int4 sp = *reinterpret_cast<const int4 *>(s_rsp + 4 * r);
+      const double ya = ybuf[sp.x < 0 ? 0 : sp.x];
+      const double yb = ybuf[sp.y < 0 ? 0 : sp.y];
+      const double yc = ybuf[sp.z < 0 ? 0 : sp.z];
       double v = exp(expo) * s_emult[r] * c[7];
       // rho^(n_r - 1) for n_r <= 3 reactants
-      if (sp[3] >= 2) v *= rho;
-      if (sp[3] >= 3) v *= rho;
-      if (sp[0] >= 0) v *= ybuf[sp[0]];
-      if (sp[1] >= 0) v *= ybuf[sp[1]];
-      if (sp[2] >= 0) v *= ybuf[sp[2]];
+      if (sp.w >= 2) v *= rho;
+      if (sp.w >= 3) v *= rho;
+      v *= (sp.x >= 0 ? ya : 1.0);
+      v *= (sp.y >= 0 ? yb : 1.0);
+      v *= (sp.z >= 0 ? yc : 1.0);
       heat += s_q[r] * v;
       const int4 *ro = reinterpret_cast<const int4 *>(s_rout + 8 * r);
       const int4 r0 = ro[0], r1 = ro[1];
-      const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-#pragma unroll
-      for (int e = 0; e < 6; ++e) {
-        if (e < r0.x)
-          __hip_atomic_fetch_add(&facc[ent[e] >> 8], (double)(signed char)(ent[e] & 0xff) * v,
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-      }
+      Unroll<6>::run([&]<int E>() __attribute__((always_inline)) {
+        if (E < ne) {
+          const Ent en = ent_of<E>(r0, r1);
+          __hip_atomic_fetch_add(&facc[en.sp], en.w * v, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+      });
     };
     for (int r = q; r < R; r += 2 * L) {
       one(r);
@@ -871,14 +907,20 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             expo += hr * fG;
             dl += hr * (-1.5 * fG * tinv);  // d(h G)/dT
           }
-          const int *sp = s_rsp + 4 * r;
+          const int4 spv = *reinterpret_cast<const int4 *>(s_rsp + 4 * r);
+          const int sp[4] = {spv.x, spv.y, spv.z, spv.w};
+          // unconditional slot loads (an absent slot reads entry 0 and
+          // stands for 1)
+          const double fa = fy[sp[0] < 0 ? 0 : sp[0]];
+          const double fb = fy[sp[1] < 0 ? 0 : sp[1]];
+          const double fc = fy[sp[2] < 0 ? 0 : sp[2]];
           double pre = exp(expo) * s_emult[r] * c[7];
           // rho^(n_r - 1) for n_r <= 3 reactants
           if (sp[3] >= 2) pre *= frho;
           if (sp[3] >= 3) pre *= frho;
-          const double ya = sp[0] >= 0 ? fy[sp[0]] : 1.0;
-          const double yb = sp[1] >= 0 ? fy[sp[1]] : 1.0;
-          const double yc = sp[2] >= 0 ? fy[sp[2]] : 1.0;
+          const double ya = sp[0] >= 0 ? fa : 1.0;
+          const double yb = sp[1] >= 0 ? fb : 1.0;
+          const double yc = sp[2] >= 0 ? fc : 1.0;
           double full = pre;
           if (sp[0] >= 0) full *= ya;
           if (sp[1] >= 0) full *= yb;
@@ -894,7 +936,6 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           if (sp[1] >= 0) g[2] *= yb;
           const int4 *ro = reinterpret_cast<const int4 *>(s_rout + 8 * r);
           const int4 r0 = ro[0], r1 = ro[1];
-          const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
           const double qc = s_qcv[r];
 #pragma unroll
           for (int aa = 0; aa < 4; ++aa) {
@@ -902,13 +943,13 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             if (col >= 0) {
               if (!isfinite(g[aa])) jbad = 1;
               const double val = ascale * g[aa];
-#pragma unroll
-              for (int e = 0; e < 6; ++e) {
-                if (e < r0.x)
-                  __hip_atomic_fetch_add(&fM[(ent[e] >> 8) * MS + col],
-                                         (double)(signed char)(ent[e] & 0xff) * val,
-                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-              }
+              Unroll<6>::run([&]<int E>() __attribute__((always_inline)) {
+                if (E < ne) {
+                  const Ent en = ent_of<E>(r0, r1);
+                  __hip_atomic_fetch_add(&fM[en.sp * MS + col], en.w * val, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+              });
               __hip_atomic_fetch_add(&fM[N * MS + col], qc * val, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
@@ -916,12 +957,13 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           if constexpr (SCR) {
             // dR_r/dG = h_r R_r, gathered per row for the rank-one term
             const double u = hr * full;
-#pragma unroll
-            for (int e = 0; e < 6; ++e) {
-              if (e < r0.x)
-                __hip_atomic_fetch_add(&uacc[ent[e] >> 8], (double)(signed char)(ent[e] & 0xff) * u,
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-            }
+            Unroll<6>::run([&]<int E>() __attribute__((always_inline)) {
+              if (E < ne) {
+                const Ent en = ent_of<E>(r0, r1);
+                __hip_atomic_fetch_add(&uacc[en.sp], en.w * u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+              }
+            });
             __hip_atomic_fetch_add(&uacc[N], qc * u, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
           }
@@ -990,14 +1032,19 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               for (int j = K; j < NP; ++j) fy[j] = LU[0][j];
             }
             wave_lds_sync();
+            // every lane reads its slot's pivot row (in bounds for idle slots
+            // too), so the loads are not held behind the branch below
+            double pr[NP];
+#pragma unroll
+            for (int j = K; j < NP; ++j) pr[j] = fy[j];
+            const double rinv = 1.0 / pr[K];
             if (mine && frow) {
-              const double rinv = 1.0 / fy[K];
               if (pos == K) fdinv = rinv;
               if (pos > K) {
                 const double l = LU[0][K] * rinv;
                 LU[0][K] = l;
 #pragma unroll
-                for (int j = K + 1; j < NP; ++j) LU[0][j] -= l * fy[j];
+                for (int j = K + 1; j < NP; ++j) LU[0][j] -= l * pr[j];
               }
             }
             wave_lds_sync();

@@ -29,6 +29,7 @@ struct NetTables {
   const int *col_ent;  // [nsl] (r << 2) | slot, ascending in r then slot
   const signed char *nu8;  // [N][R] dense nu_ir
   const int *rout;     // [R][8]: count, then (species << 8) | (nu_ir & 0xff) for nu_ir != 0
+  int max_ent;         // largest count in rout (0..6)
   const double *screen;  // [R] screening strengths h_r, or nullptr
   const double *wsq;     // [N] A_j^2 (screening)
 };
