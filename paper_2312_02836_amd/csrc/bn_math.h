@@ -62,4 +62,20 @@ __host__ __device__ inline double bn_log(double x) {
   return y;
 }
 
+// x / d correctly rounded, given inv_d = 1 / d correctly rounded: the
+// product q = x inv_d is within one unit in the last place of x / d, the
+// remainder x - q d is exact in one fused multiply-add, and q + r inv_d then
+// rounds to the correctly rounded quotient (Markstein's correction step)
+// wherever that quotient is a normal number; a subnormal one may be off by
+// one unit in its last place.  Three dependent operations instead of a full
+// division, for a divisor that is fixed for a whole launch.  An infinite or
+// NaN quotient is returned as the product gives it (inf / d = inf, NaN stays
+// NaN).
+__host__ __device__ inline double bn_div_by(double x, double d, double inv_d) {
+  const double q = x * inv_d;
+  const double r = fma(-q, d, x);
+  const double c = fma(r, inv_d, q);
+  return __builtin_isfinite(q) ? c : q;
+}
+
 }  // namespace bn

@@ -400,6 +400,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   const int ne = nt.max_ent;  // entries per reaction, padded (ent_of)
   int n = nt.n;  // re-derived opaquely in every iteration, like q
   const int MS = SH::ms(n);
+  // the norms' mean over the n components, sum / n, without a division
+  const double dn_sz = (double)n, inv_n = 1.0 / dn_sz;
   const int MROWS = SH::rows(n);
   const size_t FB = SH::fb(n);
 
@@ -466,7 +468,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const double z = v[s] * inv[s];
       if (comp(s) < n) acc += z * z;
     }
-    return sqrt(gsum<L>(acc) / (double)n);
+    return sqrt(bn_div_by(gsum<L>(acc), dn_sz, inv_n));
   };
 
   // change of step size by ratio rh on rows 0..k of D: D <- (R(rh) U)^T D,
@@ -479,7 +481,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const int i = comp(s);
       double dcol[KMAX + 1];
 #pragma unroll
-      for (int b = 0; b <= KMAX; ++b) dcol[b] = (b <= k) ? Dl[b * NP + i] : 0.0;
+      for (int b = 0; b <= KMAX; ++b) {
+        const double x = Dl[b * NP + i];  // read unconditionally, used for b <= k
+        dcol[b] = (b <= k) ? x : 0.0;
+      }
       // rows b > k are zero in dcol, so their terms add exactly nothing; the
       // node m = 0 reproduces D_0; entries aa <= k use only m <= aa <= k
       double v[KMAX + 1];
@@ -759,12 +764,16 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             const int i = comp(s);
             double sa = Dl[i];
             double sb = 0.0;
+            // rows 1..KMAX are read whatever k is (rows above k are unused),
+            // so no load waits behind a branch on k
+            double dr[KMAX + 1];
+#pragma unroll
+            for (int j = 1; j <= KMAX; ++j) dr[j] = Dl[j * NP + i];
 #pragma unroll
             for (int j = 1; j <= KMAX; ++j) {
               if (j <= k) {
-                const double dj = Dl[j * NP + i];
-                sa += dj;
-                sb += gamma_of(j) * dj;
+                sa += dr[j];
+                sb += gamma_of(j) * dr[j];
               }
             }
             yp[s] = sa;
@@ -1272,9 +1281,12 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             double rate = 0.0;
             if (it > 0) {
               rate = dn / dprev;
-              double rp = rate;  // rate^(4 - it)
-              for (int e = it + 1; e < kNewtonMaxIt; ++e) rp *= rate;
-              if (rate >= 1.0 || rp / (1.0 - rate) * dn > kNewtonTol) fail = 1;
+              // predicted error after the remaining iterations,
+              // rate^(4 - it) dn / (1 - rate) > tol, with it = 1..3 and
+              // 1 - rate > 0 multiplied out
+              const double r2 = rate * rate;
+              const double rp = it == 1 ? r2 * rate : (it == 2 ? r2 : rate);
+              if (rate >= 1.0 || rp * dn > kNewtonTol * (1.0 - rate)) fail = 1;
             }
             if (!fail) {
 #pragma unroll
@@ -1282,7 +1294,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
                 yv[s] += tmp[s];
                 dd[s] += tmp[s];
               }
-              if (dn == 0.0 || (it > 0 && rate / (1.0 - rate) * dn < kNewtonTol)) {
+              // converged: rate dn / (1 - rate) < tol (here rate < 1)
+              if (dn == 0.0 || (it > 0 && rate * dn < kNewtonTol * (1.0 - rate))) {
                 converged = 1;
               } else {
                 dprev = dn;
@@ -1320,12 +1333,18 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 #pragma unroll
             for (int s = 0; s < S; ++s) {
               const int i = comp(s);
+              double dr[KMAX + 1];  // rows 0..KMAX, read before the branches on k
+#pragma unroll
+              for (int j = 0; j <= KMAX; ++j) dr[j] = Dl[j * NP + i];
               const double dk2 = dd[s] - Dl[(k + 1) * NP + i];
               Dl[(k + 1) * NP + i] = dd[s];
               double up = dd[s];
-              for (int j = k; j >= 0; --j) {
-                up = Dl[j * NP + i] + up;
-                Dl[j * NP + i] = up;
+#pragma unroll
+              for (int j = KMAX; j >= 0; --j) {
+                if (j <= k) {
+                  up = dr[j] + up;
+                  Dl[j * NP + i] = up;
+                }
               }
               if (i < n) {
                 const double zm = (Dl[k * NP + i] / (double)k) * isc[s];
@@ -1350,8 +1369,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             if (n_eq >= k + 1) {
               em_acc = gsum<L>(em_acc);
               ep_acc = gsum<L>(ep_acc);
-              const double em = (k > 1) ? sqrt(em_acc / (double)n) : INFINITY;
-              const double ep = (k < KMAX) ? sqrt(ep_acc / (double)n) : INFINITY;
+              const double em = (k > 1) ? sqrt(bn_div_by(em_acc, dn_sz, inv_n)) : INFINITY;
+              const double ep = (k < KMAX) ? sqrt(bn_div_by(ep_acc, dn_sz, inv_n)) : INFINITY;
               // the factors norm^(-1/(order+1)) of orders k-1, k, k+1,
               // compared by their logarithms; one exponential for the best
               const double lm = bn_log(em) * (-1.0 / (double)k);

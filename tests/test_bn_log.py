@@ -1,9 +1,16 @@
-"""The kernels' FP64 logarithm (artanh reduction, written without
-contraction so the host evaluates exactly what the device does) against
-numpy's log in extended precision: within one unit in the last place over
-the temperature range, error-norm magnitudes, the whole positive normal
-range, subnormals and the neighbourhoods of 1 and sqrt(2), and the IEEE
-special values."""
+"""The kernels' own FP64 arithmetic helpers, built for the host from the same
+source.
+
+* The logarithm (artanh reduction, written without contraction so the host
+  evaluates exactly what the device does) against numpy's log in extended
+  precision: within one unit in the last place over the temperature range,
+  error-norm magnitudes, the whole positive normal range, subnormals and the
+  neighbourhoods of 1 and sqrt(2), and the IEEE special values.
+* The division by a launch constant (the system size n in the error norms'
+  mean): bit-identical to the IEEE quotient x / n for every n the kernels
+  take wherever the quotient is a normal number (sums of squares of all
+  magnitudes), and for 0, inf and NaN; a subnormal quotient is within one
+  unit of its last place."""
 import ctypes
 import os
 import shutil
@@ -18,14 +25,19 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
 @pytest.fixture(scope="module")
-def bn_log(tmp_path_factory):
+def hostlib(tmp_path_factory):
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
     out = str(tmp_path_factory.mktemp("bnlog") / "libbnlog.so")
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-O2", "-fPIC", "-shared", "-I", CSRC,
                     os.path.join(HERE, "native", "bn_log_host.hip"), "-o", out],
                    check=True, capture_output=True)
-    lib = ctypes.CDLL(out)
+    return ctypes.CDLL(out)
+
+
+@pytest.fixture(scope="module")
+def bn_log(hostlib):
+    lib = hostlib
 
     def f(x):
         x = np.ascontiguousarray(x, dtype=np.float64)
@@ -68,3 +80,26 @@ def test_exact_points_and_specials(bn_log):
     assert y[4] == -np.inf and y[5] == -np.inf
     assert np.isnan(y[6]) and np.isnan(y[8]) and np.isnan(y[9])
     assert y[7] == np.inf
+
+
+def test_div_by_launch_constant_is_the_ieee_quotient(hostlib):
+    rng = np.random.default_rng(1)
+    lib = hostlib
+    lib.bn_div_by_host.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_long]
+    # sums of squares of scaled components: every magnitude from the
+    # smallest normal to the largest finite value, plus exact small integers
+    x = np.concatenate([10.0 ** rng.uniform(-307, 308, 60_000),
+                        rng.uniform(0.0, 1.0, 20_000) * 64.0,
+                        np.arange(0.0, 4097.0),
+                        [0.0, np.finfo(np.float64).max, np.finfo(np.float64).tiny]])
+    for n in range(1, 130):
+        y = np.empty_like(x)
+        lib.bn_div_by_host(x.ctypes.data, float(n), y.ctypes.data, x.size)
+        ref = x / float(n)
+        normal = ref >= np.finfo(np.float64).tiny
+        assert np.array_equal(y[normal], ref[normal]), (n, x[normal & (y != ref)][:5])
+        assert np.all(np.abs(y - ref)[~normal] <= 2.0 ** -1074), n
+    special = np.array([np.inf, np.nan, -0.0])
+    y = np.empty_like(special)
+    lib.bn_div_by_host(special.ctypes.data, 14.0, y.ctypes.data, special.size)
+    assert y[0] == np.inf and np.isnan(y[1]) and y[2] == 0.0
