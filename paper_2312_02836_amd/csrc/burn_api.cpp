@@ -258,6 +258,8 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
     }
     rout[8 * r] = c;
     if (c > max_ent) max_ent = c;
+    // entries past the count: coefficient 0 on the first listed species
+    for (int e = c; e < 6; ++e) rout[8 * r + 1 + e] = c ? (rout[8 * r + 1] & ~0xff) : 0;
   }
 
   auto *net = new bn_network();

@@ -309,14 +309,15 @@ struct Tabs {
   const int *rsp, *rout;
 };
 
-// Entry e (0..5) of a reaction's species list (rout row ro0, ro1).  Past
-// the reaction's own count the list is padded, up to the network's largest
-// count, with coefficient-0 entries on its first listed species, so that all
-// lanes of a wave take the same number of entries without a branch per entry.
-// A padded entry adds w x = +-0 (it leaves the accumulator unchanged unless
-// that holds -0), or NaN when x is not finite; x is then a rate or a rate
-// derivative of the same reaction, and that reaction's heat term (q x) or the
-// caller's finiteness check already marks the evaluation as failed.
+// Entry E (0..5) of a reaction's species list (rout row ro0, ro1).  Past the
+// reaction's own count the table holds coefficient-0 entries on its first
+// listed species, so that all lanes of a wave take the same number of
+// entries (the network's largest count) without a branch or a select per
+// entry.  A padded entry adds w x = +-0, which leaves the accumulator
+// unchanged (an accumulator that starts at +0 never holds -0), or NaN when x
+// is not finite; x is then a rate or a rate derivative of the same reaction,
+// and that reaction's heat term (q x) or the caller's finiteness check
+// already marks the evaluation as failed.
 struct Ent {
   int sp;    // species
   double w;  // nu_ir, or 0 for a padded entry
@@ -324,18 +325,15 @@ struct Ent {
 template <int E>
 __device__ __forceinline__ Ent ent_of(const int4 &ro0, const int4 &ro1) {
   static_assert(E >= 0 && E < 6, "a reaction changes at most 6 species");
-  constexpr int kLane = E + 1;  // position in the row after the count
-  const int raw = kLane == 1   ? ro0.y
-                  : kLane == 2 ? ro0.z
-                  : kLane == 3 ? ro0.w
-                  : kLane == 4 ? ro1.x
-                  : kLane == 5 ? ro1.y
-                               : ro1.z;
-  const bool on = E < ro0.x;
-  const int e = on ? raw : ro0.y;
+  const int raw = E == 0   ? ro0.y
+                  : E == 1 ? ro0.z
+                  : E == 2 ? ro0.w
+                  : E == 3 ? ro1.x
+                  : E == 4 ? ro1.y
+                           : ro1.z;
   Ent r;
-  r.sp = e >> 8;
-  r.w = (double)(on ? (int)(signed char)(e & 0xff) : 0);
+  r.sp = raw >> 8;
+  r.w = (double)(int)(signed char)(raw & 0xff);
   return r;
 }
 

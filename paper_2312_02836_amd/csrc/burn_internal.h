@@ -28,7 +28,8 @@ struct NetTables {
   const int *col_off;  // [N + 1] start of each species' reactant-slot list
   const int *col_ent;  // [nsl] (r << 2) | slot, ascending in r then slot
   const signed char *nu8;  // [N][R] dense nu_ir
-  const int *rout;     // [R][8]: count, then (species << 8) | (nu_ir & 0xff) for nu_ir != 0
+  const int *rout;     // [R][8]: count, then (species << 8) | (nu_ir & 0xff) for nu_ir != 0,
+                       // padded to 6 entries with coefficient 0 on the first species
   int max_ent;         // largest count in rout (0..6)
   const double *screen;  // [R] screening strengths h_r, or nullptr
   const double *wsq;     // [N] A_j^2 (screening)
