@@ -597,9 +597,14 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
       if (!SH::COMPACT || K < n) {
         const double xk = gbcast<L, K % L>(b[K / L]);
+        // the factor column masked to the strictly lower part (a select
+        // that does not wait for xk) and an unconditional update: b - 0 xk
+        // is b
 #pragma unroll
-        for (int s = K / L; s < S; ++s)
-          if (comp(s) > K) b[s] -= LU[s][K] * xk;
+        for (int s = K / L; s < S; ++s) {
+          const double lk = comp(s) > K ? LU[s][K] : 0.0;
+          b[s] = fma(-lk, xk, b[s]);
+        }
       }
     });
     // back substitution with the upper factor: at step K component K is
@@ -610,8 +615,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       if (!SH::COMPACT || K < n) {
         const double xk = gbcast<L, K % L>(b[K / L] * dinv[K / L]);
 #pragma unroll
-        for (int s = 0; s <= K / L; ++s)
-          if (comp(s) < K) b[s] -= LU[s][K] * xk;
+        for (int s = 0; s <= K / L; ++s) {
+          const double uk = comp(s) < K ? LU[s][K] : 0.0;  // strictly upper part
+          b[s] = fma(-uk, xk, b[s]);
+        }
       }
     });
 #pragma unroll
@@ -1026,6 +1033,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               }
             }
             int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
+            // every row's reciprocal of its entry K, computed while the
+            // arg-max runs; the pivot row hands its own over in place of
+            // that entry, so no division waits for the pivot row's loads
+            const double rown = 1.0 / LU[0][K];
             gargmax_key<FL>(v, key);
             nan_k = gor<FL>(nan_k);
             if (!(v > 0.0) || nan_k) fsing = 1;
@@ -1035,16 +1046,17 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               else if (pos == bp) pos = K;
             }
             if (mine && fi == (key & 255)) {
+              fy[K] = rown;
 #pragma unroll
-              for (int j = K; j < NP; ++j) fy[j] = LU[0][j];
+              for (int j = K + 1; j < NP; ++j) fy[j] = LU[0][j];
             }
             wave_lds_sync();
             // every lane reads its slot's pivot row (in bounds for idle slots
-            // too), so the loads are not held behind the branch below
+            // too)
             double pr[NP];
 #pragma unroll
             for (int j = K; j < NP; ++j) pr[j] = fy[j];
-            const double rinv = 1.0 / pr[K];
+            const double rinv = pr[K];
             if (mine && frow) {
               if (pos == K) fdinv = rinv;
               if (pos > K) {
