@@ -194,13 +194,16 @@ __device__ __forceinline__ double gsum(double v) {
   }
 }
 
-template <int G, int LV = 0>
+// Any of the group's active lanes nonzero (1 or 0): one ballot and the
+// group's bits of it, instead of a chain of exchanges.
+template <int G>
 __device__ __forceinline__ int gor(int v) {
-  if constexpr (LV < n_levels<G>()) {
-    v |= xch_i<G, LV>(v);
-    return gor<G, LV + 1>(v);
+  const unsigned long long m = __ballot(v != 0);
+  if constexpr (G >= 64) {
+    return m != 0ULL;
   } else {
-    return v;
+    const int base = (int)(threadIdx.x & 63) & ~(G - 1);
+    return ((m >> base) & ((1ULL << G) - 1)) != 0ULL;
   }
 }
 

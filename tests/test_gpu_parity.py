@@ -110,6 +110,33 @@ def test_synth13_full_size_sampled(gpu, oracle):
     net.close()
 
 
+def _entry_edge_network():
+    """Four species of mass 1 whose reactions change 2, 0, 4, 2 and 2 species:
+    the kernels pad every reaction's species list to the largest count (4)
+    with coefficient-0 entries, and a reaction that changes no species (a
+    catalysed heat source, A + B -> A + B) is padded whole."""
+    reactants = np.array([[0, -1, -1], [0, 1, -1], [0, 1, -1], [2, 3, -1], [1, 1, -1]])
+    products = np.array([[1, -1, -1], [0, 1, -1], [2, 3, -1], [2, 2, -1], [1, 2, -1]])
+    coef = np.zeros((5, 7))
+    coef[:, 0] = np.log([2.0, 1.5, 0.8, 0.6, 0.4])
+    coef[:, 1] = [-0.3, -0.5, -0.2, -0.1, -0.4]  # a1 / T: heat feeds back
+    spec = synth.NetworkSpec("entries5", np.ones(4, dtype=np.int32), reactants, products, coef,
+                             np.array([1.0, 2.0, 0.5, 0.0, 0.3]), 50.0)
+    spec.validate()
+    return spec
+
+
+def test_reactions_changing_no_or_many_species(gpu, oracle):
+    spec = _entry_edge_network()
+    cells = _random_cells(spec, 300, 11)
+    g, o = _run_both(gpu, oracle, spec, cells, 2.0)
+    _assert_parity(g, o)
+    assert np.all(g[2] == 0)
+    # every reaction with q > 0, the one that changes no species among them,
+    # releases heat, so T rises in every cell
+    assert np.all(g[1] > cells.T)
+
+
 def test_log_multipliers(gpu, oracle):
     cfg = synth.config(2, n_cells=700)
     lm = np.random.default_rng(3).normal(0.0, 0.5, cfg.networks[0].n_reactions)
