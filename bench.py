@@ -2,9 +2,10 @@
 
 Workloads (--workload):
   synth13  (default) burn of the synthetic 13-species / 30-reaction
-           network, 65,536 cells, dt = 1e-2, one plain kernel launch (static
-           map of cells to lane groups, the fastest schedule for one small
-           network), with the persistent launch timed beside it;
+           network, 65,536 cells, dt = 1e-2, one persistent launch (a lane
+           group that finishes a cell takes the next from a device work
+           queue), with the plain launch (static map of cells to lane groups)
+           timed beside it;
   mixed4   four networks (13/30, 21/60, 35/100, 50/150), 65,536 cells each,
            in ONE persistent launch with a device work queue; the plain
            kernel (one launch per network) is timed beside it;
@@ -39,10 +40,10 @@ KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_body.h",
                   "paper_2312_02836_amd/csrc/burn_plain.h",
                   "paper_2312_02836_amd/csrc/burn_multi.hip",
                   "paper_2312_02836_amd/csrc/burn_internal.h"]
-TRAFFIC_FILE = "profiles/burn_plain_kernel__synth13_30__65536cells__hbm_traffic.txt"
+TRAFFIC_FILE = "profiles/burn_multi_kernel__synth13_30__65536cells__hbm_traffic.txt"
 
 WORKLOADS = {
-    "synth13": dict(config=2, cells=65536, mode="plain",
+    "synth13": dict(config=2, cells=65536, mode="persistent",
                     text="burn of one synthetic 13-species/30-reaction network, {cells} cells, "
                          "dt=1e-2, rtol 1e-6, atol 1e-10"),
     "mixed4": dict(config=4, cells=65536, mode="persistent",
@@ -235,7 +236,7 @@ def main() -> int:
         cpu = cpu_baseline(batches, cfg, args.cpu_seconds)
 
     traffic = None
-    if (args.workload == "synth13" and wl["mode"] == "plain"
+    if (args.workload == "synth13" and wl["mode"] == "persistent"
             and (n_cells, args.lanes, args.block_waves) == (65536, 0, 0)):
         traffic = measured_traffic()
     config = {"workload": wl["text"].format(cells=n_cells), "cells_per_network": n_cells,

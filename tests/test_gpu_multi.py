@@ -221,6 +221,19 @@ def _sampled(oracle, spec, cells, t_end, out, n_sample, seed, min_counter_equal=
     assert np.all(g[2] == 0)
 
 
+def test_synth13_persistent_full_size_sampled(gpu, oracle):
+    """The headline benchmark workload as bench.py times it: the 13/30
+    network, 65,536 cells, one persistent launch with the default shape; the
+    oracle recomputes a seeded sample of 2,048 cells one by one."""
+    cfg = synth.config(2)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    assert cells.n_cells == 65536
+    net = gpu.Network(spec)
+    out = gpu.burn_multi([(net, cells.Y, cells.rho, cells.T)], cfg.t_end, RTOL, ATOL)[0]
+    _sampled(oracle, spec, cells, cfg.t_end, out, 2048, 3)
+    net.close()
+
+
 def test_mixed4_full_size_sampled(gpu, oracle):
     """The mixed benchmark workload as bench.py times it: four networks,
     65,536 cells each, one persistent launch with the default shapes; the
