@@ -131,7 +131,9 @@ typedef struct {
   int32_t lanes_per_cell; /* 0 = the network's launch choice (tuned or default);
                              otherwise 4, 8, 16, 32 or 64 */
   int32_t block_waves;    /* 0 = automatic; waves per workgroup (tuning) */
-  int32_t reserved;
+  int32_t order_cells;    /* burn_batch_multi only: 1 = hand each network's
+                             cells out costliest first (see there), 0 = in
+                             index order; ignored by the other calls */
 } bn_burn_opts;
 
 /* burn_batch with knobs (opts may be NULL: defaults). */
@@ -174,6 +176,13 @@ typedef struct {
  * queue counter per item, rounded up to 256 bytes). */
 size_t burn_batch_multi_workspace_bytes(int32_t n_items);
 
+/* Device workspace of burn_batch_multi with opts->order_cells = 1: the bytes
+ * above plus, per item with cells, 256 four-byte bucket counters and 8 bytes
+ * per cell (the probe's step sizes and the queue permutation), each region
+ * on a 256-byte boundary.  items is HOST [n_items]; NULL gives the
+ * unordered size. */
+size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_item *items);
+
 /* Burn the cells of up to BN_MAX_ITEMS networks (same dt and tolerances) in
  * ONE persistent kernel launch with a device work queue: the grid is sized to
  * the GPU, and each lane group that finishes a cell takes the next unstarted
@@ -184,13 +193,24 @@ size_t burn_batch_multi_workspace_bytes(int32_t n_items);
  *   items      HOST [n_items]   the batches (networks on the current device)
  *   opts       HOST or NULL     max_steps and block_waves are honoured;
  *                               lanes_per_cell must be 0 (each network uses its
- *                               launch choice, see bn_network_autotune)
+ *                               launch choice, see bn_network_autotune);
+ *                               order_cells 0 or 1 (else BN_EINVAL)
  *   workspace  DEVICE           >= burn_batch_multi_workspace_bytes(n_items)
- *                               bytes, 8-byte aligned, caller-owned; it must
- *                               not be used by another launch in flight
- * The call enqueues a small counter-reset kernel and the burn kernel on
- * `stream` and nothing else (no allocation, no memset, no synchronization),
- * so a sequence of calls can be captured into a HIP graph and replayed.
+ *                               bytes (with order_cells = 1:
+ *                               burn_batch_multi_order_workspace_bytes), 8-byte
+ *                               aligned, caller-owned; it must not be used by
+ *                               another launch in flight
+ * With order_cells = 1 each network's queue hands out its cells in order of
+ * increasing initial step size h0 (the integrator's first-step estimate
+ * 0.01 ||y0|| / ||f(y0)||, the same weighted norms as in the burn), so the
+ * stiffest cells start first and the launch ends on short ones; a probe
+ * kernel evaluates one right-hand side per cell and a counting sort over
+ * 128 buckets of log2 h0 (two per octave) builds the order.  Only the order
+ * of work changes, not any cell's result.
+ * The call enqueues small counter-reset kernels, the order kernels when
+ * asked, and the burn kernel on `stream` and nothing else (no allocation, no
+ * memset, no synchronization), so a sequence of calls can be captured into a
+ * HIP graph and replayed.
  * Returns BN_SUCCESS or a negative code (nothing enqueued). */
 int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, double rtol,
                      double atol, const bn_burn_opts *opts, void *workspace,

@@ -21,7 +21,8 @@ COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "
 # Every symbol include/burn.h declares.
 EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "bn_network_n_reactions", "burn_batch", "burn_batch_ex",
-           "burn_batch_multi_workspace_bytes", "burn_batch_multi", "bn_network_autotune",
+           "burn_batch_multi_workspace_bytes", "burn_batch_multi_order_workspace_bytes",
+           "burn_batch_multi", "bn_network_autotune",
            "bn_network_set_launch", "bn_network_get_launch",
            "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
            "burn_batch_adjoint_backward", "burn_batch_adjoint", "burn_batch_sdc",
@@ -39,7 +40,7 @@ class NetworkDesc(C.Structure):
 
 class BurnOpts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("lanes_per_cell", C.c_int32),
-                ("block_waves", C.c_int32), ("reserved", C.c_int32)]
+                ("block_waves", C.c_int32), ("order_cells", C.c_int32)]
 
 
 class BatchItem(C.Structure):
@@ -82,6 +83,8 @@ def lib() -> C.CDLL:
     L.burn_batch_ex.restype = C.c_int
     L.burn_batch_multi_workspace_bytes.argtypes = [C.c_int32]
     L.burn_batch_multi_workspace_bytes.restype = C.c_size_t
+    L.burn_batch_multi_order_workspace_bytes.argtypes = [C.c_int32, C.POINTER(BatchItem)]
+    L.burn_batch_multi_order_workspace_bytes.restype = C.c_size_t
     L.burn_batch_multi.argtypes = [C.c_int32, C.POINTER(BatchItem), C.c_double, C.c_double,
                                    C.c_double, C.POINTER(BurnOpts), vp, C.c_size_t, vp]
     L.burn_batch_multi.restype = C.c_int

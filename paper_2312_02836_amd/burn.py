@@ -156,19 +156,23 @@ class MultiBurn:
     one kernel launch with a device work queue.
 
     The device arrays are bound at construction (float64 contiguous device
-    tensors, updated in place), so ``run()`` enqueues exactly a counter-reset
-    kernel and the burn kernel on the current stream: it allocates nothing
-    and can be captured into a graph (``capture()``) and replayed.
+    tensors, updated in place), so ``run()`` enqueues only kernels on the
+    current stream (counter resets, with ``order_cells`` the queue-order
+    probe and counting sort, and the burn): it allocates nothing and can be
+    captured into a graph (``capture()``) and replayed.  ``order_cells``
+    hands each network's cells out stiffest first (smallest initial step);
+    results do not depend on it.
     """
 
     def __init__(self, batches, dt: float, rtol: float = 1e-6, atol: float = 1e-10, *,
                  max_steps: int = 0, block_waves: int = 0, want_status: bool = True,
-                 want_counters: bool = True, device: Optional[torch.device] = None):
+                 want_counters: bool = True, order_cells: bool = True,
+                 device: Optional[torch.device] = None):
         device = device or torch.device("cuda", torch.cuda.current_device())
         if len(batches) > _lib.MAX_ITEMS:
             raise ValueError(f"at most {_lib.MAX_ITEMS} batches per launch")
         self.dt, self.rtol, self.atol = float(dt), float(rtol), float(atol)
-        self.opts = _lib.BurnOpts(int(max_steps), 0, int(block_waves), 0)
+        self.opts = _lib.BurnOpts(int(max_steps), 0, int(block_waves), int(bool(order_cells)))
         self.outputs = []
         items = (_lib.BatchItem * max(1, len(batches)))()
         for j, b in enumerate(batches):
@@ -184,7 +188,10 @@ class MultiBurn:
                                       cnt.data_ptr() if cnt is not None else None)
         self.nets = [b[0] for b in batches]  # keep the handles alive
         self.items, self.n_items = items, len(batches)
-        nb = _lib.lib().burn_batch_multi_workspace_bytes(max(1, self.n_items))
+        if order_cells:
+            nb = _lib.lib().burn_batch_multi_order_workspace_bytes(self.n_items, items)
+        else:
+            nb = _lib.lib().burn_batch_multi_workspace_bytes(max(1, self.n_items))
         self.workspace = torch.empty(nb, dtype=torch.uint8, device=device)
         self.graph = None
 

@@ -418,6 +418,24 @@ size_t burn_batch_multi_workspace_bytes(int32_t n_items) {
   return (((size_t)n_items * sizeof(unsigned long long)) + 255) / 256 * 256;
 }
 
+namespace {
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+// Per item of an ordered launch: the bucket counters, then h0 and the
+// permutation of its cells, each on a 256-byte boundary.
+size_t order_item_bytes(int64_t n_cells) {
+  return align256(2 * bn::ORDER_BUCKETS * sizeof(unsigned)) +
+         align256((size_t)n_cells * sizeof(float)) + align256((size_t)n_cells * sizeof(int32_t));
+}
+}  // namespace
+
+size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_item *items) {
+  size_t s = burn_batch_multi_workspace_bytes(n_items);
+  if (!items) return s;
+  for (int j = 0; j < n_items; ++j)
+    if (items[j].n_cells > 0) s += order_item_bytes(items[j].n_cells);
+  return s;
+}
+
 int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, double rtol,
                      double atol, const bn_burn_opts *opts, void *workspace,
                      size_t workspace_bytes, void *stream) {
@@ -432,6 +450,7 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
   if (o.lanes_per_cell != 0)
     return fail(BN_EINVAL, "lanes_per_cell must be 0 for burn_batch_multi");
   if (o.block_waves < 0 || o.block_waves > 4) return fail(BN_EINVAL, "block_waves must be 0..4");
+  if (o.order_cells != 0 && o.order_cells != 1) return fail(BN_EINVAL, "order_cells must be 0 or 1");
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
   DeviceLimits lim;
@@ -517,9 +536,12 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
       assign(W);
     }
   }
-  const size_t need = burn_batch_multi_workspace_bytes((int32_t)its.size());
+  const size_t need = o.order_cells ? burn_batch_multi_order_workspace_bytes(n_items, items)
+                                    : burn_batch_multi_workspace_bytes((int32_t)its.size());
   if (!workspace || workspace_bytes < need)
-    return fail(BN_EINVAL, "workspace missing or smaller than burn_batch_multi_workspace_bytes");
+    return fail(BN_EINVAL, o.order_cells
+                               ? "workspace missing or smaller than burn_batch_multi_order_workspace_bytes"
+                               : "workspace missing or smaller than burn_batch_multi_workspace_bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 8)
     return fail(BN_EINVAL, "workspace must be 8-byte aligned");
   // costliest cells first, so the tail of the launch is made of cheap cells
@@ -552,6 +574,24 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
   hipError_t e = bn::launch_zero(m.queue, m.n_items, st);
   if (e != hipSuccess)
     return fail(BN_EHIP, std::string("counter reset launch failed: ") + hipGetErrorString(e));
+  if (o.order_cells) {
+    // each item's queue hands out its stiffest cells (smallest initial step)
+    // first, so the launch ends on short cells
+    char *p = static_cast<char *>(workspace) + burn_batch_multi_workspace_bytes(n_items);
+    for (int j = 0; j < m.n_items; ++j) {
+      const int64_t n = m.item[j].n_cells;
+      unsigned *hist = reinterpret_cast<unsigned *>(p);
+      float *key = reinterpret_cast<float *>(p + align256(2 * bn::ORDER_BUCKETS * sizeof(unsigned)));
+      int32_t *perm = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(key) +
+                                                  align256((size_t)n * sizeof(float)));
+      p += order_item_bytes(n);
+      e = bn::launch_zero(reinterpret_cast<unsigned long long *>(hist), bn::ORDER_BUCKETS, st);
+      if (e == hipSuccess) e = bn::launch_order(m.item[j], key, perm, hist, lim.lds_block, st);
+      if (e != hipSuccess)
+        return fail(BN_EHIP, std::string("queue order launch failed: ") + hipGetErrorString(e));
+      m.item[j].perm = perm;
+    }
+  }
   e = bn::launch_multi(m, (int)grid, W, st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return BN_SUCCESS;

@@ -387,9 +387,14 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
 // SCR every rate carries the synthetic screening factor exp(h_r G),
 // G = sqrt(rho (1 + sum_j A_j^2 Y_j)) T^(-3/2), and the Jacobian its terms
 // (a rank-one composition part u_i dG/dY_j and dG/dT in the T column).
-template <int L, int S, bool QUEUE, bool REC = false, bool SRC = false, bool SCR = false>
+// With PROBE a cell stops after the initial step size h0 and writes only
+// h0 to a.key (the queue order of the persistent kernel).  In the queue
+// mode a.perm, when set, maps queue positions to cells.
+template <int L, int S, bool QUEUE, bool REC = false, bool SRC = false, bool SCR = false,
+          bool PROBE = false>
 __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, double *wb,
                                           int64_t first_cell, unsigned long long *queue) {
+  static_assert(!(PROBE && (QUEUE || REC)), "the order probe runs on the static map alone");
   using SH = Shape<L, S>;
   constexpr int NP = SH::NP, CPW = SH::CPW, FL = SH::FL, FC = SH::FC;
   constexpr int DS = SH::DS, YS = SH::YS, ECH = SH::ECH;
@@ -636,6 +641,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   int k = 1, n_eq = 0, jac_cur = 0, lu_ok = 0, it = 0, need_attempt = 0, new_step = 0;
   int fresh_newton = 0, first_jac = 0, defer_it = 0;
   int f_pre = 0, okf_pre = 1;  // F already holds f(predictor), computed while waiting
+  float probe_h0 = __builtin_inff();  // PROBE: h0, or +inf for a cell that fails first
   double t = 0.0, h = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, err = 0.0, h0 = 0.0, d1 = 0.0;
 
   // outputs of the group's cell: state (if integration started), status and
@@ -732,7 +738,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         base = ((unsigned long long)hi << 32) | lo;
         const unsigned long long below = lmask & ((1ULL << (cw * L)) - 1ULL);
         const unsigned long long idx = base + (unsigned long long)__popcll(below);
-        if (phase == PH_LOAD) load_cell(idx < (unsigned long long)C ? (int64_t)idx : C);
+        if (phase == PH_LOAD) {
+          int64_t c = C;
+          if (idx < (unsigned long long)C) c = a.perm ? (int64_t)a.perm[idx] : (int64_t)idx;
+          load_cell(c >= 0 ? c : C);
+        }
       }
     }
     // static map: a finished cell stays done and is written after the loop
@@ -1230,9 +1240,10 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           d1 = wrms(F, isc);
           h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
           if (h0 > t_end) h0 = t_end;
+          if constexpr (PROBE) probe_h0 = (float)h0;
 #pragma unroll
           for (int s = 0; s < S; ++s) yv[s] = yv[s] + h0 * F[s];
-          phase = PH_F1;
+          phase = PROBE ? PH_DONE : PH_F1;
         }
       } else if (phase == PH_F1) {
         double df[S];
@@ -1445,7 +1456,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     if (pend != 0.0 && phase == PH_NEWTON) rescale(k, pend);
   }
   if constexpr (!QUEUE) {
-    if (phase == PH_DONE) write_out();
+    if constexpr (PROBE) {
+      if (phase == PH_DONE && q == 0) a.key[cell] = probe_h0;
+    } else {
+      if (phase == PH_DONE) write_out();
+    }
   }
 }
 

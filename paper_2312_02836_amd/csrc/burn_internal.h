@@ -57,6 +57,12 @@ struct BurnArgs {
   // Constant per-cell source [n][n_cells] added to the right-hand side
   // (simplified-SDC forcing; nullptr otherwise).
   const double *src;
+  // Persistent kernel: queue position -> cell, a permutation of
+  // [0, n_cells) (nullptr: position = cell).
+  const int32_t *perm;
+  // Order probe: per cell the integrator's initial step size h0
+  // (+inf for a cell that fails before it), [n_cells].
+  float *key;
 };
 
 // Shapes: lanes per cell L, slots per lane S (the system is padded to
@@ -98,6 +104,14 @@ struct MultiArgs {
   size_t wave_doubles;            // LDS doubles per wave area (max over items)
 };
 hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream);
+
+// Queue order of one item of the persistent kernel, costliest cells first:
+// a probe launch computes every cell's initial step size h0 (one right-hand
+// side), then a counting sort over ORDER_BUCKETS buckets of log2 h0 writes
+// a.perm.  hist is 2 * ORDER_BUCKETS zero-initialized counters.
+constexpr int ORDER_BUCKETS = 128;
+hipError_t launch_order(const BurnArgs &a, float *key, int32_t *perm, unsigned *hist,
+                        size_t lds_block, hipStream_t stream);
 
 // Sensitivity runs (discrete adjoint with respect to the log-rate
 // multipliers).  The replay / adjoint kernels take one cell per wave.

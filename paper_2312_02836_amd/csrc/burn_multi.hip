@@ -79,6 +79,79 @@ burn_multi_kernel(MultiArgs m) {
   }
 }
 
+// ---- queue order (costliest cells first) ----
+
+// One right-hand side per cell: the integrator's initial step size h0 into
+// a.key (static map of cells to lane groups, as the plain kernel).
+template <int L, int S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+burn_probe_kernel(BurnArgs a, int block_waves) {
+  using SH = Shape<L, S>;
+  extern __shared__ double smem[];
+  load_tables(a.net, a.log_mult, smem);
+  __syncthreads();
+  const Tabs tb = tabs_at(smem, a.net.R);
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  double *wb = smem + tab_doubles_of(a.net.R) + (size_t)wave * SH::wave_doubles(a.net.n);
+  const int64_t first = ((int64_t)blockIdx.x * block_waves + wave) * SH::CPW + lane / L;
+  run_cells<L, S, false, false, false, false, true>(a, tb, wb, first, nullptr);
+}
+
+// Bucket of a cell: two per octave of h0, the smallest steps (the stiffest
+// cells, which take the most work) first; +inf and NaN (failed cells) last.
+__device__ __forceinline__ int order_bucket(float h0) {
+  if (!(h0 < __builtin_inff())) return ORDER_BUCKETS - 1;
+  if (!(h0 > 0.0f)) return 0;
+  const int b = (int)floorf(2.0f * log2f(h0)) + (ORDER_BUCKETS - 8);
+  return b < 0 ? 0 : (b > ORDER_BUCKETS - 1 ? ORDER_BUCKETS - 1 : b);
+}
+
+// hist[b] += number of cells in bucket b (per-block counts in LDS first).
+__global__ void __launch_bounds__(256) order_hist_kernel(const float *key, int64_t n,
+                                                         unsigned *hist) {
+  __shared__ unsigned lh[ORDER_BUCKETS];
+  for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) atomicAdd(&lh[order_bucket(key[c])], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x)
+    if (lh[b]) atomicAdd(&hist[b], lh[b]);
+}
+
+// hist[ORDER_BUCKETS + b] = first position of bucket b (exclusive prefix).
+__global__ void order_scan_kernel(unsigned *hist) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    unsigned s = 0;
+    for (int b = 0; b < ORDER_BUCKETS; ++b) {
+      hist[ORDER_BUCKETS + b] = s;
+      s += hist[b];
+    }
+  }
+}
+
+// perm[position] = cell: every block reserves a range per bucket, then its
+// cells take consecutive positions in it.
+__global__ void __launch_bounds__(256) order_scatter_kernel(const float *key, int64_t n,
+                                                            unsigned *hist, int32_t *perm) {
+  __shared__ unsigned lh[ORDER_BUCKETS], base[ORDER_BUCKETS];
+  for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) lh[b] = 0;
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  unsigned rank = 0;
+  if (c < n) {
+    b = order_bucket(key[c]);
+    rank = atomicAdd(&lh[b], 1u);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < ORDER_BUCKETS; j += blockDim.x)
+    base[j] = lh[j] ? atomicAdd(&hist[ORDER_BUCKETS + j], lh[j]) : 0u;
+  __syncthreads();
+  if (c < n) perm[base[b] + rank] = (int32_t)c;
+}
+
 __global__ void zero_kernel(unsigned long long *p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ULL;
@@ -148,6 +221,44 @@ hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream)
     }
   }
 #undef BN_MULTI
+  return hipGetLastError();
+}
+
+template <int L, int S>
+hipError_t launch_probe_t(const BurnArgs &a, size_t lds_block, hipStream_t stream) {
+  using SH = Shape<L, S>;
+  int bw = 4;
+  auto lds_of = [&](int w) {
+    return 8 * (tab_doubles_of(a.net.R) + (size_t)w * SH::wave_doubles(a.net.n));
+  };
+  while (bw > 1 && lds_of(bw) > lds_block) bw /= 2;
+  if (lds_of(bw) > lds_block) return hipErrorInvalidValue;
+  const int64_t cells_per_block = (int64_t)SH::CPW * bw;
+  const int64_t blocks = (a.n_cells + cells_per_block - 1) / cells_per_block;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((burn_probe_kernel<L, S>), dim3((unsigned)blocks), dim3(64 * bw), lds_of(bw),
+                     stream, a, bw);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const BurnArgs &item, float *key, int32_t *perm, unsigned *hist,
+                        size_t lds_block, hipStream_t stream) {
+  const int64_t n = item.n_cells;
+  if (n <= 0) return hipSuccess;
+  if (n > 0x7fffffff) return hipErrorInvalidValue;
+  BurnArgs a = item;
+  a.key = key;
+  a.perm = nullptr;
+  const int sz = a.net.n;
+  hipError_t e = sz <= 8    ? launch_probe_t<8, 1>(a, lds_block, stream)
+                 : sz <= 16 ? launch_probe_t<16, 1>(a, lds_block, stream)
+                 : sz <= 32 ? launch_probe_t<32, 1>(a, lds_block, stream)
+                            : launch_probe_t<64, 1>(a, lds_block, stream);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, stream, key, n, hist);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, hist);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, key, n, hist, perm);
   return hipGetLastError();
 }
 

@@ -115,6 +115,16 @@ def test_multi_and_tuning_reject_bad_arguments_on_host(L):
                               None) in (_lib.BN_SUCCESS, _lib.BN_EHIP)
     assert L.burn_batch_multi_workspace_bytes(1) == 256
     assert L.burn_batch_multi_workspace_bytes(8) == 256
+    # ordered queue: per item with cells 1 KiB of bucket counters plus h0 and
+    # the permutation (4 + 4 bytes per cell), each region 256-byte aligned
+    two = (_lib.BatchItem * 2)()
+    two[0].n_cells, two[1].n_cells = 1000, 0
+    assert L.burn_batch_multi_order_workspace_bytes(2, None) == 256
+    assert L.burn_batch_multi_order_workspace_bytes(2, two) == 256 + 1024 + 4096 + 4096
+    order_bad = _lib.BurnOpts(0, 0, 0, 2)
+    assert L.burn_batch_multi(1, items, 1e-2, 1e-6, 1e-10, C.byref(order_bad), None, 0,
+                              None) == _lib.BN_EINVAL
+    assert b"order_cells" in L.bn_last_error()
     n = C.c_int32(5)
     assert L.bn_network_autotune(None, 10, None, None, None, 1e-2, 1e-6, 1e-10, None, 0, None,
                                  0, C.byref(n), None) == _lib.BN_EINVAL

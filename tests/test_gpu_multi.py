@@ -221,6 +221,34 @@ def _sampled(oracle, spec, cells, t_end, out, n_sample, seed, min_counter_equal=
     assert np.all(g[2] == 0)
 
 
+def test_ordered_queue_changes_only_the_order(gpu):
+    """The cost-ordered queue (stiffest cells first) changes only the order of
+    work: every cell's state, status and counters are bitwise those of the
+    index-ordered launch; two networks of different shapes and ragged sizes
+    in one launch, plus a cell with bad input (ordered last)."""
+    import torch
+    cfg = synth.config(4, n_cells=4000)
+    nets = [gpu.Network(s) for s in cfg.networks[:2]]
+    batches = []
+    for c, m in zip(cfg.cells[:2], (3001, 1777)):
+        sub = c.subset(np.arange(m))
+        T = sub.T.copy()
+        T[5] = -1.0          # bad input
+        batches.append((sub.Y, sub.rho, T))
+    runs = []
+    for order in (False, True):
+        outs = gpu.burn_multi([(n, Y, rho, T) for n, (Y, rho, T) in zip(nets, batches)],
+                              cfg.t_end, RTOL, ATOL, order_cells=order)
+        torch.cuda.synchronize()
+        runs.append([[x.cpu().numpy() for x in o] for o in outs])
+    for a, b in zip(*runs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y, equal_nan=True)
+    assert runs[1][0][2][5] == 4 and runs[1][1][2][5] == 4
+    for n in nets:
+        n.close()
+
+
 def test_synth13_persistent_full_size_sampled(gpu, oracle):
     """The headline benchmark workload as bench.py times it: the 13/30
     network, 65,536 cells, one persistent launch with the default shape; the
