@@ -177,9 +177,10 @@ typedef struct {
 size_t burn_batch_multi_workspace_bytes(int32_t n_items);
 
 /* Device workspace of burn_batch_multi with opts->order_cells = 1: the bytes
- * above plus, per item with cells, 256 four-byte bucket counters and 8 bytes
- * per cell (the probe's step sizes and the queue permutation), each region
- * on a 256-byte boundary.  items is HOST [n_items]; NULL gives the
+ * above plus, per item with cells, 256 four-byte bucket counters and
+ * 8 (N + 8) bytes per cell (the probe's step size, the cell's position, and
+ * position-ordered copies of its state, T, rho, status and counters), each
+ * region on a 256-byte boundary.  items is HOST [n_items]; NULL gives the
  * unordered size. */
 size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_item *items);
 
@@ -204,9 +205,11 @@ size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_it
  * increasing initial step size h0 (the integrator's first-step estimate
  * 0.01 ||y0|| / ||f(y0)||, the same weighted norms as in the burn), so the
  * stiffest cells start first and the launch ends on short ones; a probe
- * kernel evaluates one right-hand side per cell and a counting sort over
- * 128 buckets of log2 h0 (two per octave) builds the order.  Only the order
- * of work changes, not any cell's result.
+ * kernel evaluates one right-hand side per cell, a counting sort over 128
+ * buckets of log2 h0 (two per octave) builds the order, the cells' arrays
+ * are copied into the workspace in that order before the burn (so cells
+ * that run at nearby times share memory lines) and copied back after it.
+ * Only the order of work changes, not any cell's result.
  * The call enqueues small counter-reset kernels, the order kernels when
  * asked, and the burn kernel on `stream` and nothing else (no allocation, no
  * memset, no synchronization), so a sequence of calls can be captured into a

@@ -420,11 +420,30 @@ size_t burn_batch_multi_workspace_bytes(int32_t n_items) {
 
 namespace {
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
-// Per item of an ordered launch: the bucket counters, then h0 and the
-// permutation of its cells, each on a 256-byte boundary.
-size_t order_item_bytes(int64_t n_cells) {
-  return align256(2 * bn::ORDER_BUCKETS * sizeof(unsigned)) +
-         align256((size_t)n_cells * sizeof(float)) + align256((size_t)n_cells * sizeof(int32_t));
+// Per item of an ordered launch, each region on a 256-byte boundary: the
+// bucket counters, h0 and the position of every cell, then the staged
+// (position-ordered) state, T, rho, status and counters.
+struct OrderLayout {
+  size_t hist, key, pos, Y, T, rho, status, counters, total;
+};
+OrderLayout order_layout(int64_t n, int N) {
+  OrderLayout l{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  l.hist = take(2 * bn::ORDER_BUCKETS * sizeof(unsigned));
+  l.key = take((size_t)n * sizeof(float));
+  l.pos = take((size_t)n * sizeof(int32_t));
+  l.Y = take((size_t)n * N * sizeof(double));
+  l.T = take((size_t)n * sizeof(double));
+  l.rho = take((size_t)n * sizeof(double));
+  l.status = take((size_t)n * sizeof(int32_t));
+  l.counters = take((size_t)n * 8 * sizeof(int32_t));
+  l.total = o;
+  return l;
 }
 }  // namespace
 
@@ -432,7 +451,8 @@ size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_it
   size_t s = burn_batch_multi_workspace_bytes(n_items);
   if (!items) return s;
   for (int j = 0; j < n_items; ++j)
-    if (items[j].n_cells > 0) s += order_item_bytes(items[j].n_cells);
+    if (items[j].n_cells > 0)
+      s += order_layout(items[j].n_cells, items[j].net ? items[j].net->N : 0).total;
   return s;
 }
 
@@ -574,26 +594,44 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
   hipError_t e = bn::launch_zero(m.queue, m.n_items, st);
   if (e != hipSuccess)
     return fail(BN_EHIP, std::string("counter reset launch failed: ") + hipGetErrorString(e));
+  // ordered: each item's cells are staged in order of increasing initial
+  // step size (stiffest first), burnt in that order and written back
+  bn::BurnArgs orig[BN_MAX_ITEMS];
+  int32_t *posv[BN_MAX_ITEMS] = {};
   if (o.order_cells) {
-    // each item's queue hands out its stiffest cells (smallest initial step)
-    // first, so the launch ends on short cells
     char *p = static_cast<char *>(workspace) + burn_batch_multi_workspace_bytes(n_items);
     for (int j = 0; j < m.n_items; ++j) {
-      const int64_t n = m.item[j].n_cells;
-      unsigned *hist = reinterpret_cast<unsigned *>(p);
-      float *key = reinterpret_cast<float *>(p + align256(2 * bn::ORDER_BUCKETS * sizeof(unsigned)));
-      int32_t *perm = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(key) +
-                                                  align256((size_t)n * sizeof(float)));
-      p += order_item_bytes(n);
+      const bn::BurnArgs a = m.item[j];
+      const OrderLayout l = order_layout(a.n_cells, a.net.N);
+      unsigned *hist = reinterpret_cast<unsigned *>(p + l.hist);
+      float *key = reinterpret_cast<float *>(p + l.key);
+      int32_t *pos = reinterpret_cast<int32_t *>(p + l.pos);
+      bn::BurnArgs s = a;
+      s.Y = reinterpret_cast<double *>(p + l.Y);
+      s.T = reinterpret_cast<double *>(p + l.T);
+      s.rho = reinterpret_cast<const double *>(p + l.rho);
+      s.status = a.status ? reinterpret_cast<int32_t *>(p + l.status) : nullptr;
+      s.counters = a.counters ? reinterpret_cast<int32_t *>(p + l.counters) : nullptr;
+      p += l.total;
       e = bn::launch_zero(reinterpret_cast<unsigned long long *>(hist), bn::ORDER_BUCKETS, st);
-      if (e == hipSuccess) e = bn::launch_order(m.item[j], key, perm, hist, lim.lds_block, st);
+      if (e == hipSuccess) e = bn::launch_order(a, key, pos, hist, lim.lds_block, st);
+      if (e == hipSuccess) e = bn::launch_stage_in(a, s, pos, st);
       if (e != hipSuccess)
         return fail(BN_EHIP, std::string("queue order launch failed: ") + hipGetErrorString(e));
-      m.item[j].perm = perm;
+      orig[j] = a;
+      posv[j] = pos;
+      m.item[j] = s;
     }
   }
   e = bn::launch_multi(m, (int)grid, W, st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  if (o.order_cells) {
+    for (int j = 0; j < m.n_items; ++j) {
+      e = bn::launch_stage_out(orig[j], m.item[j], posv[j], st);
+      if (e != hipSuccess)
+        return fail(BN_EHIP, std::string("write-back launch failed: ") + hipGetErrorString(e));
+    }
+  }
   return BN_SUCCESS;
 }
 

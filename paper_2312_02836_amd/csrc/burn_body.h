@@ -388,8 +388,7 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
 // G = sqrt(rho (1 + sum_j A_j^2 Y_j)) T^(-3/2), and the Jacobian its terms
 // (a rank-one composition part u_i dG/dY_j and dG/dT in the T column).
 // With PROBE a cell stops after the initial step size h0 and writes only
-// h0 to a.key (the queue order of the persistent kernel).  In the queue
-// mode a.perm, when set, maps queue positions to cells.
+// h0 to a.key (the queue order of the persistent kernel).
 template <int L, int S, bool QUEUE, bool REC = false, bool SRC = false, bool SCR = false,
           bool PROBE = false>
 __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, double *wb,
@@ -738,11 +737,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         base = ((unsigned long long)hi << 32) | lo;
         const unsigned long long below = lmask & ((1ULL << (cw * L)) - 1ULL);
         const unsigned long long idx = base + (unsigned long long)__popcll(below);
-        if (phase == PH_LOAD) {
-          int64_t c = C;
-          if (idx < (unsigned long long)C) c = a.perm ? (int64_t)a.perm[idx] : (int64_t)idx;
-          load_cell(c >= 0 ? c : C);
-        }
+        if (phase == PH_LOAD) load_cell(idx < (unsigned long long)C ? (int64_t)idx : C);
       }
     }
     // static map: a finished cell stays done and is written after the loop

@@ -57,9 +57,6 @@ struct BurnArgs {
   // Constant per-cell source [n][n_cells] added to the right-hand side
   // (simplified-SDC forcing; nullptr otherwise).
   const double *src;
-  // Persistent kernel: queue position -> cell, a permutation of
-  // [0, n_cells) (nullptr: position = cell).
-  const int32_t *perm;
   // Order probe: per cell the integrator's initial step size h0
   // (+inf for a cell that fails before it), [n_cells].
   float *key;
@@ -107,11 +104,21 @@ hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream)
 
 // Queue order of one item of the persistent kernel, costliest cells first:
 // a probe launch computes every cell's initial step size h0 (one right-hand
-// side), then a counting sort over ORDER_BUCKETS buckets of log2 h0 writes
-// a.perm.  hist is 2 * ORDER_BUCKETS zero-initialized counters.
+// side), then a counting sort over ORDER_BUCKETS buckets of log2 h0 gives
+// every cell its position pos[cell].  hist is 2 * ORDER_BUCKETS
+// zero-initialized counters.  The item's arrays are then staged in position
+// order (stage_in), burnt in index order, and written back (stage_out), so
+// that cells that run at nearby times also share memory lines.
 constexpr int ORDER_BUCKETS = 128;
-hipError_t launch_order(const BurnArgs &a, float *key, int32_t *perm, unsigned *hist,
+hipError_t launch_order(const BurnArgs &a, float *key, int32_t *pos, unsigned *hist,
                         size_t lds_block, hipStream_t stream);
+// staged copy of an item: st.Y, st.T, st.rho, st.status, st.counters point
+// to position-ordered arrays of the item's size (status/counters null when
+// the item's are)
+hipError_t launch_stage_in(const BurnArgs &a, const BurnArgs &st, const int32_t *pos,
+                           hipStream_t stream);
+hipError_t launch_stage_out(const BurnArgs &a, const BurnArgs &st, const int32_t *pos,
+                            hipStream_t stream);
 
 // Sensitivity runs (discrete adjoint with respect to the log-rate
 // multipliers).  The replay / adjoint kernels take one cell per wave.

@@ -131,10 +131,10 @@ __global__ void order_scan_kernel(unsigned *hist) {
   }
 }
 
-// perm[position] = cell: every block reserves a range per bucket, then its
-// cells take consecutive positions in it.
+// pos[cell] = its queue position: every block reserves a range per bucket,
+// then its cells take consecutive positions in it.
 __global__ void __launch_bounds__(256) order_scatter_kernel(const float *key, int64_t n,
-                                                            unsigned *hist, int32_t *perm) {
+                                                            unsigned *hist, int32_t *pos) {
   __shared__ unsigned lh[ORDER_BUCKETS], base[ORDER_BUCKETS];
   for (int b = threadIdx.x; b < ORDER_BUCKETS; b += blockDim.x) lh[b] = 0;
   __syncthreads();
@@ -149,7 +149,33 @@ __global__ void __launch_bounds__(256) order_scatter_kernel(const float *key, in
   for (int j = threadIdx.x; j < ORDER_BUCKETS; j += blockDim.x)
     base[j] = lh[j] ? atomicAdd(&hist[ORDER_BUCKETS + j], lh[j]) : 0u;
   __syncthreads();
-  if (c < n) perm[base[b] + rank] = (int32_t)c;
+  if (c < n) pos[c] = (int32_t)(base[b] + rank);
+}
+
+// Staging: position-ordered copies of an item's arrays (one thread per cell,
+// reading or writing the caller's arrays in cell order).
+__global__ void __launch_bounds__(256) stage_in_kernel(BurnArgs a, BurnArgs st,
+                                                       const int32_t *pos) {
+  const int64_t n = a.n_cells;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int64_t p = pos[c];
+  for (int i = 0; i < a.net.N; ++i) st.Y[(int64_t)i * n + p] = a.Y[(int64_t)i * n + c];
+  st.T[p] = a.T[c];
+  const_cast<double *>(st.rho)[p] = a.rho[c];
+}
+
+__global__ void __launch_bounds__(256) stage_out_kernel(BurnArgs a, BurnArgs st,
+                                                        const int32_t *pos) {
+  const int64_t n = a.n_cells;
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int64_t p = pos[c];
+  for (int i = 0; i < a.net.N; ++i) a.Y[(int64_t)i * n + c] = st.Y[(int64_t)i * n + p];
+  a.T[c] = st.T[p];
+  if (a.status) a.status[c] = st.status[p];
+  if (a.counters)
+    for (int k = 0; k < 8; ++k) a.counters[(int64_t)k * n + c] = st.counters[(int64_t)k * n + p];
 }
 
 __global__ void zero_kernel(unsigned long long *p, int n) {
@@ -241,14 +267,13 @@ hipError_t launch_probe_t(const BurnArgs &a, size_t lds_block, hipStream_t strea
   return hipGetLastError();
 }
 
-hipError_t launch_order(const BurnArgs &item, float *key, int32_t *perm, unsigned *hist,
+hipError_t launch_order(const BurnArgs &item, float *key, int32_t *pos, unsigned *hist,
                         size_t lds_block, hipStream_t stream) {
   const int64_t n = item.n_cells;
   if (n <= 0) return hipSuccess;
   if (n > 0x7fffffff) return hipErrorInvalidValue;
   BurnArgs a = item;
   a.key = key;
-  a.perm = nullptr;
   const int sz = a.net.n;
   hipError_t e = sz <= 8    ? launch_probe_t<8, 1>(a, lds_block, stream)
                  : sz <= 16 ? launch_probe_t<16, 1>(a, lds_block, stream)
@@ -258,7 +283,23 @@ hipError_t launch_order(const BurnArgs &item, float *key, int32_t *perm, unsigne
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, stream, key, n, hist);
   hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, hist);
-  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, key, n, hist, perm);
+  hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, key, n, hist, pos);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_in(const BurnArgs &a, const BurnArgs &st, const int32_t *pos,
+                           hipStream_t stream) {
+  if (a.n_cells <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.n_cells + 255) / 256);
+  hipLaunchKernelGGL(stage_in_kernel, dim3(blocks), dim3(256), 0, stream, a, st, pos);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_out(const BurnArgs &a, const BurnArgs &st, const int32_t *pos,
+                            hipStream_t stream) {
+  if (a.n_cells <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.n_cells + 255) / 256);
+  hipLaunchKernelGGL(stage_out_kernel, dim3(blocks), dim3(256), 0, stream, a, st, pos);
   return hipGetLastError();
 }
 
