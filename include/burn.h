@@ -177,8 +177,8 @@ typedef struct {
 size_t burn_batch_multi_workspace_bytes(int32_t n_items);
 
 /* Device workspace of burn_batch_multi with opts->order_cells = 1: the bytes
- * above plus, per item with cells, 256 four-byte bucket counters and
- * 8 (N + 8) bytes per cell (the probe's step size, the cell's position, and
+ * above plus, per item with cells, 256 four-byte bucket counters, 8 queue
+ * counters of 8 bytes and 8 (N + 8) bytes per cell (the probe's step size, the cell's position, and
  * position-ordered copies of its state, T, rho, status and counters), each
  * region on a 256-byte boundary.  items is HOST [n_items]; NULL gives the
  * unordered size. */
@@ -209,6 +209,9 @@ size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_it
  * buckets of log2 h0 (two per octave) builds the order, the cells' arrays
  * are copied into the workspace in that order before the burn (so cells
  * that run at nearby times share memory lines) and copied back after it.
+ * The order is dealt round-robin into 8 parts, one per XCD of the MI355X:
+ * a workgroup takes the cells of its own XCD's part first (they then share
+ * that XCD's L2) and those of the other parts when its own is exhausted.
  * Only the order of work changes, not any cell's result.
  * The call enqueues small counter-reset kernels, the order kernels when
  * asked, and the burn kernel on `stream` and nothing else (no allocation, no

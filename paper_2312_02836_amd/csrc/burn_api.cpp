@@ -421,10 +421,11 @@ size_t burn_batch_multi_workspace_bytes(int32_t n_items) {
 namespace {
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Per item of an ordered launch, each region on a 256-byte boundary: the
-// bucket counters, h0 and the position of every cell, then the staged
-// (position-ordered) state, T, rho, status and counters.
+// bucket counters, the per-XCD queue counters, h0 and the position of every
+// cell, then the staged (position-ordered) state, T, rho, status and
+// counters.
 struct OrderLayout {
-  size_t hist, key, pos, Y, T, rho, status, counters, total;
+  size_t hist, parts, key, pos, Y, T, rho, status, counters, total;
 };
 OrderLayout order_layout(int64_t n, int N) {
   OrderLayout l{};
@@ -435,6 +436,7 @@ OrderLayout order_layout(int64_t n, int N) {
     return at;
   };
   l.hist = take(2 * bn::ORDER_BUCKETS * sizeof(unsigned));
+  l.parts = take(bn::XCD_PARTS * sizeof(unsigned long long));
   l.key = take((size_t)n * sizeof(float));
   l.pos = take((size_t)n * sizeof(int32_t));
   l.Y = take((size_t)n * N * sizeof(double));
@@ -612,8 +614,10 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
       s.rho = reinterpret_cast<const double *>(p + l.rho);
       s.status = a.status ? reinterpret_cast<int32_t *>(p + l.status) : nullptr;
       s.counters = a.counters ? reinterpret_cast<int32_t *>(p + l.counters) : nullptr;
+      s.parts = reinterpret_cast<unsigned long long *>(p + l.parts);
       p += l.total;
       e = bn::launch_zero(reinterpret_cast<unsigned long long *>(hist), bn::ORDER_BUCKETS, st);
+      if (e == hipSuccess) e = bn::launch_zero(s.parts, bn::XCD_PARTS, st);
       if (e == hipSuccess) e = bn::launch_order(a, key, pos, hist, lim.lds_block, st);
       if (e == hipSuccess) e = bn::launch_stage_in(a, s, pos, st);
       if (e != hipSuccess)

@@ -727,7 +727,26 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     }
     if constexpr (QUEUE) {
       const unsigned long long lmask = __ballot(phase == PH_LOAD && q == 0);
-      if (lmask) {
+      if (lmask && a.parts) {
+        // ordered launch: positions of this workgroup's XCD first (cells
+        // that run on one XCD then share its L2 lines), then the other parts;
+        // at most XCD_PARTS atomics per group, then the group is idle
+        if (phase == PH_LOAD) {
+          long long got = -1;
+          if (q == 0) {
+            const int x0 = (int)(blockIdx.x % XCD_PARTS);
+            const long long per = C / XCD_PARTS, extra = C % XCD_PARTS;
+            for (int t = 0; t < XCD_PARTS && got < 0; ++t) {
+              const int x = (x0 + t) % XCD_PARTS;
+              const long long count = per + (x < extra ? 1 : 0);
+              const unsigned long long i = atomicAdd(&a.parts[x], 1ULL);
+              if ((long long)i < count) got = x * per + (x < extra ? x : extra) + (long long)i;
+            }
+          }
+          got = __builtin_bit_cast(long long, gbcast<L, 0>(__builtin_bit_cast(double, got)));
+          load_cell(got >= 0 && got < C ? (int64_t)got : C);
+        }
+      } else if (lmask) {
         // one atomic per wave; the requesting groups take consecutive indices
         const int leader = __ffsll((long long)lmask) - 1;
         unsigned long long base = 0;

@@ -60,7 +60,14 @@ struct BurnArgs {
   // Order probe: per cell the integrator's initial step size h0
   // (+inf for a cell that fails before it), [n_cells].
   float *key;
+  // Persistent kernel, ordered launch: XCD_PARTS zeroed queue counters.
+  // Positions are split into XCD_PARTS interleaved parts (part x holds the
+  // x-th, (x+8)-th, ... cells of the cost order, as one contiguous range);
+  // a workgroup takes positions from the part of its XCD and, when that is
+  // exhausted, from the others.  nullptr: one counter (MultiArgs::queue).
+  unsigned long long *parts;
 };
+constexpr int XCD_PARTS = 8;  // MI355X: workgroup b runs on XCD b % 8
 
 // Shapes: lanes per cell L, slots per lane S (the system is padded to
 // NP = L*S components) and the waves per SIMD W the kernel is compiled for

@@ -149,7 +149,12 @@ __global__ void __launch_bounds__(256) order_scatter_kernel(const float *key, in
   for (int j = threadIdx.x; j < ORDER_BUCKETS; j += blockDim.x)
     base[j] = lh[j] ? atomicAdd(&hist[ORDER_BUCKETS + j], lh[j]) : 0u;
   __syncthreads();
-  if (c < n) pos[c] = (int32_t)(base[b] + rank);
+  if (c < n) {
+    // cost rank r goes to part r % XCD_PARTS, whose range is contiguous
+    const int64_t r = (int64_t)(base[b] + rank);
+    const int64_t x = r % XCD_PARTS, per = n / XCD_PARTS, extra = n % XCD_PARTS;
+    pos[c] = (int32_t)(x * per + (x < extra ? x : extra) + r / XCD_PARTS);
+  }
 }
 
 // Staging: position-ordered copies of an item's arrays (one thread per cell,

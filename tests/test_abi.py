@@ -115,15 +115,15 @@ def test_multi_and_tuning_reject_bad_arguments_on_host(L):
                               None) in (_lib.BN_SUCCESS, _lib.BN_EHIP)
     assert L.burn_batch_multi_workspace_bytes(1) == 256
     assert L.burn_batch_multi_workspace_bytes(8) == 256
-    # ordered queue: per item with cells 1 KiB of bucket counters, h0 and the
-    # position (4 + 4 bytes per cell), staged state (8 N), T, rho (8 + 8),
+    # ordered queue: per item with cells 1 KiB of bucket counters, 8 queue
+    # counters (one per XCD), h0 and the position (4 + 4 bytes per cell), staged state (8 N), T, rho (8 + 8),
     # status (4) and counters (32 bytes per cell), each region 256-byte
     # aligned; an item without a network counts N = 0
     two = (_lib.BatchItem * 2)()
     two[0].n_cells, two[1].n_cells = 1000, 0
     assert L.burn_batch_multi_order_workspace_bytes(2, None) == 256
     assert L.burn_batch_multi_order_workspace_bytes(2, two) == (
-        256 + 1024 + 4096 + 4096 + 0 + 8192 + 8192 + 4096 + 32000)
+        256 + 1024 + 256 + 4096 + 4096 + 0 + 8192 + 8192 + 4096 + 32000)
     order_bad = _lib.BurnOpts(0, 0, 0, 2)
     assert L.burn_batch_multi(1, items, 1e-2, 1e-6, 1e-10, C.byref(order_bad), None, 0,
                               None) == _lib.BN_EINVAL
