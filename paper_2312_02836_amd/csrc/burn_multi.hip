@@ -1,5 +1,6 @@
-// burn_multi.hip -- the persistent multi-network kernel, the counter reset
-// kernel, and the host-side shape dispatch and LDS sizing for all kernels.
+// burn_multi.hip -- the persistent multi-network kernel, its queue-order
+// kernels (probe, counting sort, staging), the counter reset kernel, and the
+// host-side shape dispatch and LDS sizing for all kernels.
 //
 // The kernel is built for two waves per SIMD (the narrow shapes, whose
 // registers fit half the file) and for one (the wide ones).
@@ -13,6 +14,14 @@
 // cell early takes the next one at once, so cells of uneven stiffness do not
 // leave lanes idle until the slowest cell of a static batch is done, and the
 // tails of the different networks overlap instead of adding up.
+//
+// Queue order (ordered launches): a probe runs the burn body of every cell
+// up to its initial step size h0, a counting sort over buckets of log2 h0
+// ranks the cells stiffest first, and the rank is dealt round-robin into one
+// part per XCD.  The cells' arrays are staged in that position order, so a
+// workgroup, which takes positions from its own XCD's part first, reads and
+// writes lines that the same XCD's L2 holds; the arrays are copied back to
+// cell order after the burn.
 
 #include "burn_body.h"
 
