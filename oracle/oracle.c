@@ -55,6 +55,15 @@ typedef struct {
   const double *q;          /* [R] */
   double c_v;
   const double *screen;     /* [R] screening strengths h_r, or NULL */
+  /* Test hook, 0 in every real run.  A nonzero value changes one rounding
+   * step of the method (and nothing else) to measure how far two correct
+   * implementations that round differently can drift apart:
+   *   1  rate constants of reactions r = 0, 3, 6, ... taken one ulp up (a
+   *      second exp / cbrt / log implementation);
+   *   2  the species sums of the right-hand side taken in descending
+   *      reaction order;
+   *   3  the heat term multiplied by 1/c_v instead of divided by c_v. */
+  int rounding_probe;
 } orc_net;
 
 typedef struct {
@@ -88,6 +97,7 @@ void orc_rates(const orc_net *net, double T, const double *log_mult, double *lam
     const double *a = net->coef + 7 * r;
     double expo = a[0] + a[1] * tinv + a[2] * tm13 + a[3] * t13 + a[4] * T + a[5] * t53 + a[6] * lnT;
     double l = exp(expo);
+    if (net->rounding_probe == 1 && r % 3 == 0) l = nextafter(l, INFINITY);
     if (log_mult) l *= exp(log_mult[r]);
     lam[r] = l;
     if (dlnlam_dT) {
@@ -175,14 +185,15 @@ void orc_rhs(const orc_net *net, double rho, const double *y, const double *log_
   for (int i = 0; i < N; i++) {
     double s = 0.0;
     for (int r = 0; r < Rn; r++) {
-      int v = nu(net, i, r);
-      if (v) s += (double)v * R[r];
+      int rr = net->rounding_probe == 2 ? Rn - 1 - r : r;
+      int v = nu(net, i, rr);
+      if (v) s += (double)v * R[rr];
     }
     f[i] = s;
   }
   double e = 0.0;
   for (int r = 0; r < Rn; r++) e += net->q[r] * R[r];
-  f[N] = e / net->c_v;
+  f[N] = net->rounding_probe == 3 ? e * (1.0 / net->c_v) : e / net->c_v;
 }
 
 /* Analytic Jacobian J[i*n + j] = d f_i / d y_j (row-major, n = N+1).
@@ -359,10 +370,7 @@ static int all_finite(int n, const double *v) {
 /* One cell                                                                  */
 /* ------------------------------------------------------------------------ */
 
-#define K_MAX 5
-#define SAFETY 0.9
 #define MIN_FACTOR 0.2
-#define MAX_FACTOR 10.0
 #define NEWTON_MAXIT 4
 #define NEWTON_TOL 0.03
 
@@ -384,6 +392,122 @@ typedef struct {
 static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const double *log_mult,
                           const double *src, const orc_opts *o, int32_t *cnt,
                           orc_schedule *sch);
+static void rhs_src(const orc_net *net, double rho, const double *y, const double *log_mult,
+                    const double *src, double *f);
+
+/* Initial step size (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4,
+ * the starting-step algorithm for a method of order p = 1):
+ *   s = atol + rtol |y0|, d0 = ||y0||, d1 = ||f(y0)|| (weighted RMS, scale s);
+ *   h0 = 0.01 d0 / d1, or 1e-6 if d0 or d1 is below 1e-5; h0 <= t_end;
+ *   one explicit Euler step y1 = y0 + h0 f(y0), d2 = ||f(y1) - f(y0)|| / h0;
+ *   h1 = (0.01 / max(d1, d2))^(1/(p+1)), or max(1e-6, 1e-3 h0) when
+ *   max(d1, d2) <= 1e-15 (and 1e-3 h0 when d2 is not finite);
+ *   h = min(100 h0, h1, t_end).
+ * f0 receives f(y0); *n_rhs counts the two evaluations.  Returns 0, or
+ * ORC_NONFINITE when f(y0) is not finite (then *h_out is not set). */
+static int initial_step(const orc_net *net, double rho, const double *y0, const double *log_mult,
+                        const double *src, double t_end, double rtol, double atol, double *f0,
+                        double *h_out, int *n_rhs) {
+  const int n = net->n_species + 1;
+  double s[ORC_NMAX], tmp[ORC_NMAX], f1[ORC_NMAX];
+  rhs_src(net, rho, y0, log_mult, src, f0);
+  (*n_rhs)++;
+  if (!all_finite(n, f0)) return ORC_NONFINITE;
+  for (int i = 0; i < n; i++) s[i] = atol + rtol * fabs(y0[i]);
+  double d0 = wrms(n, y0, s), d1 = wrms(n, f0, s);
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+  if (h0 > t_end) h0 = t_end;
+  for (int i = 0; i < n; i++) tmp[i] = y0[i] + h0 * f0[i];
+  rhs_src(net, rho, tmp, log_mult, src, f1);
+  (*n_rhs)++;
+  for (int i = 0; i < n; i++) tmp[i] = f1[i] - f0[i];
+  double d2 = wrms(n, tmp, s) / h0;
+  double h1;
+  if (!isfinite(d2)) {
+    h1 = 1e-3 * h0;
+  } else {
+    double dm = d1 > d2 ? d1 : d2;
+    if (dm <= 1e-15) {
+      h1 = 1e-3 * h0;
+      if (h1 < 1e-6) h1 = 1e-6;
+    } else {
+      h1 = sqrt(0.01 / dm);
+    }
+  }
+  double h = 100.0 * h0;
+  if (h1 < h) h = h1;
+  if (t_end < h) h = t_end;
+  *h_out = h;
+  return ORC_OK;
+}
+
+/* Test entry: the initial step size the integrator takes for y0 (or -1 if
+ * f(y0) is not finite). */
+double orc_initial_step(const orc_net *net, double rho, const double *y0, const double *log_mult,
+                        double t_end, double rtol, double atol) {
+  double f0[ORC_NMAX], h = -1.0;
+  int n_rhs = 0;
+  if (initial_step(net, rho, y0, log_mult, NULL, t_end, rtol, atol, f0, &h, &n_rhs) != ORC_OK)
+    return -1.0;
+  return h;
+}
+
+/* Local error estimate of an order-k step (Shampine & Reichelt 1997, BDF
+ * with kappa = 0): the corrector's total increment d = y_new - y_pred is
+ * the (k+1)-th backward difference of the solution at the new point, and
+ * the leading term of the local truncation error of BDF_k is C_k times it
+ * with the error constant C_k = 1 / (k + 1).  The norm is the weighted RMS
+ * with the scale s = atol + rtol max(|y_old|, |y_new|) componentwise, which
+ * is returned in s_out (the order choice reuses it). */
+double orc_error_norm(int n, int k, const double *d, const double *y_old, const double *y_new,
+                      double rtol, double atol, double *s_out) {
+  double tmp[ORC_NMAX];
+  for (int i = 0; i < n; i++) {
+    double a = fabs(y_old[i]), b = fabs(y_new[i]);
+    s_out[i] = atol + rtol * (a > b ? a : b);
+    tmp[i] = d[i] / (double)(k + 1);
+  }
+  return wrms(n, tmp, s_out);
+}
+
+/* Order and step-size choice after an accepted order-k step taken k+1 steps
+ * after the last change (Shampine & Reichelt 1997).  After the history
+ * update, D_k = grad^k y_{n+1} and D_{k+2} = grad^{k+2} y_{n+1}, so
+ *   err_m = ||C_{k-1} D_k|| = ||D_k / k||          (order k-1, k > 1)
+ *   err_p = ||C_{k+1} D_{k+2}|| = ||D_{k+2}/(k+2)||  (order k+1, k < 5)
+ * estimate the local truncation errors the neighbouring orders would have
+ * made, err (order k) is the step's own estimate, and each order q would
+ * allow the step ratio err_q^(-1/(q+1)).  The order with the largest ratio
+ * is taken (ties keep k, then prefer k-1); the new step ratio is
+ * min(MAX_FACTOR, SAFETY * ratio).  dk, dk2: the rows D_k and D_{k+2};
+ * s: the error test's scale.  Returns the new order; *factor the ratio. */
+#define K_MAX 5
+#define SAFETY 0.9
+#define MAX_FACTOR 10.0
+int orc_choose_order(int n, int k, double err, const double *dk, const double *dk2,
+                     const double *s, double *factor) {
+  double tmp[ORC_NMAX];
+  double em = INFINITY, ep = INFINITY;
+  if (k > 1) {
+    for (int i = 0; i < n; i++) tmp[i] = dk[i] / (double)k;
+    em = wrms(n, tmp, s);
+  }
+  if (k < K_MAX) {
+    for (int i = 0; i < n; i++) tmp[i] = dk2[i] / (double)(k + 2);
+    ep = wrms(n, tmp, s);
+  }
+  double fm = pow(em, -1.0 / (double)k);
+  double f0 = pow(err, -1.0 / (double)(k + 1));
+  double fp = pow(ep, -1.0 / (double)(k + 2));
+  double best = f0;
+  int dk_ = 0;
+  if (fm > best) { best = fm; dk_ = -1; }
+  if (fp > best) { best = fp; dk_ = 1; }
+  double f = SAFETY * best;
+  if (f > MAX_FACTOR) f = MAX_FACTOR;
+  *factor = f;
+  return k + dk_;
+}
 
 /* Integrate one cell from t = 0 to t_end.  y_io holds (Y, T) on entry and
  * the last accepted state on exit.  cnt receives the eight counters.  Returns
@@ -391,6 +515,27 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
 int orc_burn_cell(const orc_net *net, double rho, double *y_io, const double *log_mult,
                   const orc_opts *o, int32_t *cnt) {
   return burn_cell_impl(net, rho, y_io, log_mult, NULL, o, cnt, NULL);
+}
+
+/* orc_burn_cell that also returns the control decisions it took: the
+ * initial step size, and per accepted step its order, its step size and the
+ * product of the history rescale ratios since the previous accepted step
+ * (arrays of cap entries; cap >= o->max_steps).  *n_rec receives the number
+ * of recorded steps. */
+int orc_burn_cell_sched(const orc_net *net, double rho, double *y_io, const double *log_mult,
+                        const orc_opts *o, int32_t *cnt, double *h_init, double *h,
+                        double *ratio, int32_t *order, int cap, int *n_rec) {
+  orc_schedule sch;
+  sch.cap = cap;
+  sch.n_steps = 0;
+  sch.h_init = 0.0;
+  sch.h = h;
+  sch.ratio = ratio;
+  sch.order = order;
+  int st = burn_cell_impl(net, rho, y_io, log_mult, NULL, o, cnt, &sch);
+  *h_init = sch.h_init;
+  *n_rec = sch.n_steps;
+  return st;
 }
 
 /* Right-hand side plus a constant per-cell source term (src NULL: none).
@@ -440,33 +585,10 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
     jac_current = 1;
   } else {
     /* Initial step (Hairer, Norsett & Wanner, vol. I, Sec. II.4, order 1). */
-    rhs_src(net, rho, y0, log_mult, src, f0);
-    cnt[C_RHS]++;
-    if (!all_finite(n, f0)) return ORC_NONFINITE;
-    for (int i = 0; i < n; i++) s[i] = atol + rtol * fabs(y0[i]);
-    double d0 = wrms(n, y0, s), d1 = wrms(n, f0, s);
-    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
-    if (h0 > t_end) h0 = t_end;
-    for (int i = 0; i < n; i++) tmp[i] = y0[i] + h0 * f0[i];
-    rhs_src(net, rho, tmp, log_mult, src, f1);
-    cnt[C_RHS]++;
-    for (int i = 0; i < n; i++) tmp[i] = f1[i] - f0[i];
-    double d2 = wrms(n, tmp, s) / h0;
-    double h1;
-    if (!isfinite(d2)) {
-      h1 = 1e-3 * h0;
-    } else {
-      double dm = d1 > d2 ? d1 : d2;
-      if (dm <= 1e-15) {
-        h1 = 1e-3 * h0;
-        if (h1 < 1e-6) h1 = 1e-6;
-      } else {
-        h1 = sqrt(0.01 / dm);
-      }
-    }
-    h = 100.0 * h0;
-    if (h1 < h) h = h1;
-    if (t_end < h) h = t_end;
+    int n_rhs = 0;
+    int ist = initial_step(net, rho, y0, log_mult, src, t_end, rtol, atol, f0, &h, &n_rhs);
+    cnt[C_RHS] += n_rhs;
+    if (ist != ORC_OK) return ist;
 
     /* History: D_0 = y0, D_1 = h f0, the rest zero; order 1. */
     if (sch) { sch->h_init = h; sch->n_steps = 0; }
@@ -571,12 +693,7 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
       }
 
       /* Error test with scale atol + rtol * max(|y_n|, |y_new|). */
-      for (int i = 0; i < n; i++) {
-        double a = fabs(D[i]), b = fabs(y[i]);
-        s2[i] = atol + rtol * (a > b ? a : b);
-        tmp[i] = d[i] / (double)(k + 1);
-      }
-      err = wrms(n, tmp, s2);
+      err = orc_error_norm(n, k, d, D, y, rtol, atol, s2);
       if (!o->fixed_order && err > 1.0) {
         double factor = SAFETY * pow(err, -1.0 / (double)(k + 1));
         if (factor < MIN_FACTOR) factor = MIN_FACTOR;
@@ -614,25 +731,8 @@ static int burn_cell_impl(const orc_net *net, double rho, double *y_io, const do
 
     /* Order and step-size selection after k+1 steps at constant h. */
     if (n_eq >= k + 1) {
-      double em = INFINITY, ep = INFINITY;
-      if (k > 1) {
-        for (int i = 0; i < n; i++) tmp[i] = D[k * n + i] / (double)k;
-        em = wrms(n, tmp, s2);
-      }
-      if (k < K_MAX) {
-        for (int i = 0; i < n; i++) tmp[i] = D[(k + 2) * n + i] / (double)(k + 2);
-        ep = wrms(n, tmp, s2);
-      }
-      double fm = pow(em, -1.0 / (double)k);
-      double f0_ = pow(err, -1.0 / (double)(k + 1));
-      double fp = pow(ep, -1.0 / (double)(k + 2));
-      double best = f0_;
-      int dk = 0;
-      if (fm > best) { best = fm; dk = -1; }
-      if (fp > best) { best = fp; dk = 1; }
-      k += dk;
-      double factor = SAFETY * best;
-      if (factor > MAX_FACTOR) factor = MAX_FACTOR;
+      double factor;
+      k = orc_choose_order(n, k, err, D + k * n, D + (k + 2) * n, s2, &factor);
       h *= factor;
       orc_rescale(n, k, D, factor);
       racc *= factor;

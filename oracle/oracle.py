@@ -8,6 +8,7 @@ contraction, OpenMP) into liboracle.so next to this file.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -23,13 +24,19 @@ STATUS = {0: "OK", 1: "MAX_STEPS", 2: "STEP_UNDERFLOW", 3: "NONFINITE", 4: "BAD_
 COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "n_solve", "order"]
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc -O2, no fast-math, no FMA contraction, OpenMP: src -> out (.so)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wno-unused-variable", src, "-o", out + ".tmp", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile liboracle.so (always when force)."""
     if force or not os.path.exists(LIB):
-        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wno-unused-variable", SRC, "-o", LIB + ".tmp", "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(LIB + ".tmp", LIB)
+        compile_source(SRC, LIB)
     return LIB
 
 
@@ -38,7 +45,7 @@ class _Net(C.Structure):
                 ("mass", C.POINTER(C.c_int32)), ("reactants", C.POINTER(C.c_int32)),
                 ("products", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_double)),
                 ("q", C.POINTER(C.c_double)), ("c_v", C.c_double),
-                ("screen", C.POINTER(C.c_double))]
+                ("screen", C.POINTER(C.c_double)), ("rounding_probe", C.c_int)]
 
 
 class _Opts(C.Structure):
@@ -55,32 +62,61 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
-        L.orc_rates.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
-        L.orc_rhs.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
-        L.orc_jac.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
-        L.orc_lu_factor.argtypes = [C.c_int, dp, ip]
-        L.orc_lu_factor.restype = C.c_int
-        L.orc_lu_solve.argtypes = [C.c_int, dp, ip, dp]
-        L.orc_rescale.argtypes = [C.c_int, C.c_int, dp, C.c_double]
-        L.orc_burn_cell.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, C.POINTER(_Opts),
-                                    C.POINTER(C.c_int32)]
-        L.orc_burn_cell.restype = C.c_int
-        L.orc_burn_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, C.POINTER(_Opts),
-                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int]
-        L.orc_burn_batch.restype = C.c_int
-        L.orc_sens_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, dp,
-                                     C.POINTER(_Opts), C.POINTER(C.c_int32),
-                                     C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32), C.c_int]
-        L.orc_sens_batch.restype = C.c_int
-        L.orc_burn_batch_src.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, dp,
-                                         C.POINTER(_Opts), C.POINTER(C.c_int32),
-                                         C.POINTER(C.c_int32), C.c_int]
-        L.orc_burn_batch_src.restype = C.c_int
-        L.orc_max_threads.restype = C.c_int
-        _lib = L
+        _lib = _bind(C.CDLL(LIB))
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Run the binding's functions against another build of the oracle
+    (tests that plant a mistake in a copy of oracle.c use this)."""
+    global _lib
+    saved = lib()
+    _lib = _bind(C.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def _bind(L):
+    """Set the argument and result types of an oracle build's functions."""
+    dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
+    L.orc_rates.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
+    L.orc_rhs.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
+    L.orc_jac.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, dp]
+    L.orc_lu_factor.argtypes = [C.c_int, dp, ip]
+    L.orc_lu_factor.restype = C.c_int
+    L.orc_lu_solve.argtypes = [C.c_int, dp, ip, dp]
+    L.orc_rescale.argtypes = [C.c_int, C.c_int, dp, C.c_double]
+    L.orc_burn_cell.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, C.POINTER(_Opts),
+                                C.POINTER(C.c_int32)]
+    L.orc_burn_cell.restype = C.c_int
+    L.orc_burn_cell_sched.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, C.POINTER(_Opts),
+                                      C.POINTER(C.c_int32), dp, dp, dp,
+                                      C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_int)]
+    L.orc_burn_cell_sched.restype = C.c_int
+    L.orc_initial_step.argtypes = [C.POINTER(_Net), C.c_double, dp, dp, C.c_double,
+                                   C.c_double, C.c_double]
+    L.orc_initial_step.restype = C.c_double
+    L.orc_error_norm.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_double, dp]
+    L.orc_error_norm.restype = C.c_double
+    L.orc_choose_order.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, dp,
+                                   C.POINTER(C.c_double)]
+    L.orc_choose_order.restype = C.c_int
+    L.orc_burn_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, C.POINTER(_Opts),
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int]
+    L.orc_burn_batch.restype = C.c_int
+    L.orc_sens_batch.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, dp,
+                                 C.POINTER(_Opts), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), dp, C.POINTER(C.c_int32), C.c_int]
+    L.orc_sens_batch.restype = C.c_int
+    L.orc_burn_batch_src.argtypes = [C.POINTER(_Net), C.c_int64, dp, dp, dp, dp, dp,
+                                     C.POINTER(_Opts), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.c_int]
+    L.orc_burn_batch_src.restype = C.c_int
+    L.orc_max_threads.restype = C.c_int
+    return L
 
 
 def _dp(a: Optional[np.ndarray]):
@@ -92,7 +128,11 @@ def _dp(a: Optional[np.ndarray]):
 class OracleNet:
     """Holds the network arrays alive and the C struct pointing at them."""
 
-    def __init__(self, spec):
+    def __init__(self, spec, rounding_probe: int = 0):
+        """rounding_probe: test hook, 0 for every real run (see orc_net in
+        oracle.c): 1 rate constants of every third reaction one ulp up, 2 the
+        right-hand side's species sums in descending reaction order, 3 the
+        heat term times 1/c_v."""
         spec.validate()
         self.spec = spec
         self.mass = np.ascontiguousarray(spec.mass, dtype=np.int32)
@@ -105,7 +145,8 @@ class OracleNet:
         i32 = C.POINTER(C.c_int32)
         self.c = _Net(spec.n_species, spec.n_reactions, self.mass.ctypes.data_as(i32),
                       self.reactants.ctypes.data_as(i32), self.products.ctypes.data_as(i32),
-                      _dp(self.coef), _dp(self.q), float(spec.c_v), _dp(self.screen))
+                      _dp(self.coef), _dp(self.q), float(spec.c_v), _dp(self.screen),
+                      int(rounding_probe))
         self.N = spec.n_species
         self.R = spec.n_reactions
         self.n = self.N + 1
@@ -181,6 +222,63 @@ def burn_cell(net: OracleNet, rho: float, y0, t_end: float, rtol: float = 1e-6,
     st = lib().orc_burn_cell(C.byref(net.c), float(rho), _dp(y), _dp(lm), C.byref(o),
                              cnt.ctypes.data_as(C.POINTER(C.c_int32)))
     return y, int(st), cnt
+
+
+def burn_cell_schedule(net: OracleNet, rho: float, y0, t_end: float, rtol: float = 1e-6,
+                       atol: float = 1e-10, log_mult=None, max_steps: int = 100000):
+    """One cell with its control decisions; returns (y_end, status,
+    counters[8], h_init, h[n], ratio[n], order[n]) over the n accepted
+    steps."""
+    y = np.array(y0, dtype=np.float64, copy=True)
+    cnt = np.zeros(8, dtype=np.int32)
+    lm = _lm(net, log_mult)
+    o = _opts(t_end, rtol, atol, max_steps)
+    cap = int(max_steps)
+    h = np.zeros(cap)
+    ratio = np.zeros(cap)
+    order = np.zeros(cap, dtype=np.int32)
+    h_init = C.c_double()
+    n_rec = C.c_int()
+    st = lib().orc_burn_cell_sched(C.byref(net.c), float(rho), _dp(y), _dp(lm), C.byref(o),
+                                   cnt.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(h_init),
+                                   _dp(h), _dp(ratio), order.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   cap, C.byref(n_rec))
+    k = n_rec.value
+    return y, int(st), cnt, h_init.value, h[:k], ratio[:k], order[:k]
+
+
+def initial_step(net: OracleNet, rho: float, y0, t_end: float, rtol: float = 1e-6,
+                 atol: float = 1e-10, log_mult=None) -> float:
+    """The integrator's initial step size for y0 (-1 if f(y0) is not finite)."""
+    y = np.ascontiguousarray(y0, dtype=np.float64)
+    lm = _lm(net, log_mult)
+    return float(lib().orc_initial_step(C.byref(net.c), float(rho), _dp(y), _dp(lm),
+                                        float(t_end), float(rtol), float(atol)))
+
+
+def error_norm(k: int, d, y_old, y_new, rtol: float, atol: float):
+    """The order-k local error estimate of a step with corrector increment d
+    from y_old to y_new; returns (err, scale)."""
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    yo = np.ascontiguousarray(y_old, dtype=np.float64)
+    yn = np.ascontiguousarray(y_new, dtype=np.float64)
+    s = np.zeros(d.shape[0])
+    e = lib().orc_error_norm(d.shape[0], int(k), _dp(d), _dp(yo), _dp(yn), float(rtol),
+                             float(atol), _dp(s))
+    return float(e), s
+
+
+def choose_order(k: int, err: float, dk, dk2, scale):
+    """The order / step choice after an accepted order-k step from the
+    updated rows D_k, D_{k+2} and the error test's scale; returns
+    (new order, step ratio)."""
+    dk = np.ascontiguousarray(dk, dtype=np.float64)
+    dk2 = np.ascontiguousarray(dk2, dtype=np.float64)
+    s = np.ascontiguousarray(scale, dtype=np.float64)
+    f = C.c_double()
+    kn = lib().orc_choose_order(dk.shape[0], int(k), float(err), _dp(dk), _dp(dk2), _dp(s),
+                                C.byref(f))
+    return int(kn), f.value
 
 
 def burn_fixed(net: OracleNet, rho: float, D_init, k: int, h: float, n_steps: int,

@@ -6,6 +6,7 @@ runs in the HIP kernels of libburn.so.
 from __future__ import annotations
 
 import ctypes as C
+import warnings
 from typing import Optional, Tuple
 
 import numpy as np
@@ -318,6 +319,12 @@ class BurnFn(torch.autograd.Function):
         run = AdjointRun(net, Y0, rho, T0, dt, rtol, atol, log_mult.detach(),
                          max_steps=max_steps, device=log_mult.device)
         Y, T, E, status = run.forward()
+        n_bad = int((status != 0).sum().item())
+        if n_bad:
+            codes = sorted(set(status[status != 0].tolist()))
+            warnings.warn(f"{n_bad} of {run.C} cells did not reach t_end (status "
+                          f"{', '.join(_lib.CELL_STATUS.get(c, str(c)) for c in codes)}); they "
+                          f"keep their last state and contribute no gradient", RuntimeWarning)
         ctx.run = run
         ctx.mark_non_differentiable(status)
         return Y.clone(), E.clone(), status

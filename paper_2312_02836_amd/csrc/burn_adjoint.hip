@@ -471,7 +471,11 @@ adjoint_kernel(AdjArgs a) {
       a.iters[C + cell] = n_lu;
     }
     if (!ok) {
-      if (lane == 0) a.status[cell] = ST_NONFINITE;
+      // the outputs keep the recording run's end state; E follows it
+      if (lane == 0) {
+        a.status[cell] = ST_NONFINITE;
+        a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
+      }
       return;
     }
     if (own) {

@@ -19,3 +19,21 @@ def oracle():
     if not os.path.exists(O.LIB):
         O.build()
     return O
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """One line per parity check of the run (cells, share of cells with the
+    oracle's decisions, largest error in tolerance units among those cells
+    and overall, error of the divergent cells against a tight reference), so
+    that the figures stay in the tail of a quiet run's output."""
+    from tests.parity import RECORD
+    if not RECORD:
+        return
+    tr = terminalreporter
+    tr.write_line("parity: test | cells | counters equal | max ewt (same counters) | max ewt "
+                  "| divergent vs tight")
+    for e in RECORD:
+        name = e["test"].split("::")[-1][:48]
+        tight = "-" if e["tight_err"] is None else f"{e['tight_err']:.2f}"
+        tr.write_line(f"parity: {name} | {e['cells']} | {e['counters_equal']:.4f} | "
+                      f"{e['max_ewt_same']:.2e} | {e['max_ewt']:.2e} | {tight}")

@@ -43,8 +43,20 @@ def summary(rep) -> str:
 # lie within 100 (rtol |y| + atol) of closed forms and tight references).
 GLOBAL_ERROR_BOUND = 100.0
 
+# Share of cells that may take another decision sequence than the oracle's.
+# On networks where no one-ulp change of the oracle's own rounding flips any
+# decision (13/30, 21/60, 35/100 at rtol 1e-6), 0.1 %: in practice none.
+DEFAULT_MIN_COUNTER_EQUAL = 0.999
+# The 50-species network: one-ulp changes of the oracle's rounding flip
+# 0.6-2 % of its cells (tests/test_oracle_rounding.py), so 3 %.
+ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL = 0.97
 
-def assert_parity(g, o, rtol, atol, *, min_counter_equal=0.99, tight=None):
+# Every parity check of the session, for the end-of-run summary (conftest).
+RECORD = []
+
+
+def assert_parity(g, o, rtol, atol, *, min_counter_equal=DEFAULT_MIN_COUNTER_EQUAL, tight=None,
+                  label=None, extra_divergent=0):
     """The parity gate.
 
     * statuses equal for every cell;
@@ -53,16 +65,29 @@ def assert_parity(g, o, rtol, atol, *, min_counter_equal=0.99, tight=None):
       component;
     * at most 1 - min_counter_equal of the cells may have taken a different
       decision sequence (a rounding-level difference can flip one accept /
-      reject or order choice; both are then valid BDF solutions).  Each such
-      cell that misses the per-component bound must still be a valid
-      solution: ``tight(idx)`` returns the oracle's (Y, T) for those cells at
-      a tolerance 1e4 times tighter, and the GPU result must lie within the
-      oracle's pinned global-error bound of it.
+      reject or order choice; both are then valid BDF solutions: the oracle
+      itself diverges that way from copies of itself that round one step
+      differently, by up to several tolerances).  Each such cell that misses
+      the per-component bound must still be a valid solution: ``tight(idx)``
+      returns the oracle's (Y, T) for those cells at a tolerance 1e4 times
+      tighter, and the GPU result must lie within the oracle's pinned
+      global-error bound of it.
+    * extra_divergent: cells allowed to diverge on top of that share (small
+      samples of a rounding-sensitive network, where the share is below one
+      cell).
     """
+    import os
     rep = compare(*g, *o, rtol, atol)
     print(summary(rep), flush=True)
+    entry = {"test": label or os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0],
+             "cells": rep["n_cells"], "counters_equal": rep["counter_equal_frac"],
+             "max_ewt_same": rep["max_ewt_same_counters"], "max_ewt": rep["max_ewt"],
+             "tight_err": None}
+    RECORD.append(entry)
     assert rep["status_equal"], "per-cell status differs"
-    assert rep["counter_equal_frac"] >= min_counter_equal, summary(rep)
+    n_div = int((~rep["same_counters"]).sum())
+    allowed = int(np.floor((1.0 - min_counter_equal) * rep["n_cells"] + 1e-9)) + extra_divergent
+    assert n_div <= allowed, (f"{n_div} cells diverge, {allowed} allowed", summary(rep))
     ewt, same = rep["per_cell_ewt"], rep["same_counters"]
     bad_same = np.nonzero((ewt > 1.0) & same)[0]
     assert bad_same.size == 0, ("cells with the oracle's decisions off by more than the "
@@ -77,5 +102,6 @@ def assert_parity(g, o, rtol, atol, *, min_counter_equal=0.99, tight=None):
         err = (np.abs(yg - yt) / (rtol * np.abs(yt) + atol)).max(axis=0)
         print(f"divergent cells {bad_div.tolist()[:10]}: error vs tight reference "
               f"{err.max():.3e} (bound {GLOBAL_ERROR_BOUND})", flush=True)
+        entry["tight_err"] = float(err.max())
         assert np.all(err <= GLOBAL_ERROR_BOUND), (bad_div, err)
     return rep

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 from paper_2312_02836_amd import synth
-from tests.parity import assert_parity
+from tests.parity import (DEFAULT_MIN_COUNTER_EQUAL, ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL,
+                          assert_parity)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +42,13 @@ def _run_gpu(B, spec, cells, t_end, gY, gE, log_mult=None, max_steps=2048):
     return out
 
 
-def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rtol=1e-6):
+# Per-cell gradients agree with the oracle's to this share of the cell's
+# largest component (observed 1-2e-11 on the 13/30 and 21/60 networks).
+GRAD_RTOL = 1e-10
+
+
+def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rtol=GRAD_RTOL,
+                   min_counter_equal=DEFAULT_MIN_COUNTER_EQUAL, extra_divergent=0):
     C = cells.n_cells
     gY, gE = _cot(spec, C, seed)
     Yg, Tg, Eg, stg, cntg, gg = _run_gpu(B, spec, cells, t_end, gY, gE, log_mult)
@@ -54,7 +61,8 @@ def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rt
         return r[0], r[1]
 
     # the replayed end state
-    rep = assert_parity((Yg, Tg, stg, cntg), (Yo, To, sto, cnto), RTOL, ATOL, tight=tight)
+    rep = assert_parity((Yg, Tg, stg, cntg), (Yo, To, sto, cnto), RTOL, ATOL, tight=tight,
+                        min_counter_equal=min_counter_equal, extra_divergent=extra_divergent)
     assert np.allclose(Eg, spec.c_v * (Tg - cells.T), rtol=1e-12, atol=1e-14)
     # gradients where both sides replayed the same schedule
     go = oracle.vjp(onet, S, gY, gE)
@@ -83,9 +91,15 @@ def test_adjoint_synth13_with_multipliers(gpu, oracle):
 
 
 def test_adjoint_synth50(gpu, oracle):
-    """50 species / 150 reactions: one cell per wave with n = 51 lanes."""
+    """50 species / 150 reactions: one cell per wave with n = 51 lanes.  This
+    network's Newton matrices are ill-conditioned enough that the rounding
+    differences of the two replays' corrected states (each solved to 1e-10 in
+    the weighted norm, by different iterations) show in the gradients at
+    ~6e-9 of their scale; the bound is 1e-8."""
     cfg = synth.config(4, n_cells=33)
-    _check_adjoint(gpu, oracle, cfg.networks[3], cfg.cells[3], cfg.t_end, seed=2)
+    _check_adjoint(gpu, oracle, cfg.networks[3], cfg.cells[3], cfg.t_end, seed=2,
+                   grad_rtol=1e-8, min_counter_equal=ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL,
+                   extra_divergent=1)
 
 
 def test_adjoint_bateman_chain(gpu, oracle):
@@ -147,6 +161,14 @@ def test_adjoint_failure_paths(gpu, oracle):
     assert np.all(gg[:, [3, 5]] == 0.0) and np.all(Eg[[3, 5]] == 0.0)
     ok = np.setdiff1d(np.arange(20), [3, 5])
     assert np.all(stg[ok] == 0)
+    # the autograd wrapper says so
+    import torch
+    net = gpu.Network(spec)
+    p = torch.zeros(spec.n_reactions, dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.warns(RuntimeWarning, match="2 of 20 cells did not reach t_end"):
+        Y, E, st = gpu.BurnFn.apply(p, net, bad.Y, bad.rho, bad.T, cfg.t_end)
+    assert torch.isfinite(E).all()
+    net.close()
     # a step budget smaller than the burn needs
     Yg, Tg, Eg, stg, cntg, gg = _run_gpu(gpu, spec, cells, cfg.t_end, gY, gE, max_steps=5)
     assert np.all(stg == 1) and np.all(gg == 0.0)
@@ -186,6 +208,7 @@ def test_adjoint21_full_size_sampled(gpu, oracle):
     same = rep["same_counters"] & (sto == 0)
     scale = np.abs(go).max(axis=0)
     err = np.abs(gg[:, idx] - go).max(axis=0)
-    print(f"adjoint full size: sample 96, same schedule {int(same.sum())}", flush=True)
-    assert same.sum() >= 90
-    assert np.all(err[same] <= 1e-6 * scale[same] + 1e-300)
+    print(f"adjoint full size: sample 96, same schedule {int(same.sum())}, max rel grad err "
+          f"{(err / np.maximum(scale, 1e-300)).max():.3e}", flush=True)
+    assert same.all()
+    assert np.all(err <= GRAD_RTOL * scale + 1e-300)

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2312_02836_amd import synth
-from tests.parity import assert_parity
+from tests.parity import DEFAULT_MIN_COUNTER_EQUAL, assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +40,8 @@ def _run_both(B, oracle, spec, cells, t_end, rtol=RTOL, atol=ATOL, log_mult=None
 _LAST = None
 
 
-def _assert_parity(g, o, rtol=RTOL, atol=ATOL, min_counter_equal=0.99, ctx=None):
+def _assert_parity(g, o, rtol=RTOL, atol=ATOL, min_counter_equal=DEFAULT_MIN_COUNTER_EQUAL,
+                   ctx=None):
     """tests.parity.assert_parity; counter-divergent cells are checked against
     a 1e4 times tighter oracle solution of the same cells (ctx, else the
     inputs of the last _run_both)."""
@@ -149,6 +150,8 @@ def test_tight_tolerance(gpu, oracle):
     g, o = _run_both(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end, rtol=1e-9, atol=1e-14)
     # At rtol 1e-9 the controller's tests sit closer to rounding level, so a
     # few more cells take a different (equally valid) decision sequence.
+    # at rtol 1e-9 one-ulp changes of the oracle's own rounding flip 1.3-2.3 %
+    # of these cells (tests/test_oracle_rounding.py)
     _assert_parity(g, o, rtol=1e-9, atol=1e-14, min_counter_equal=0.95)
 
 

@@ -202,6 +202,61 @@ def test_jacobian_vs_finite_differences(oracle, cfg):
         np.testing.assert_allclose(J, Jfd, rtol=1e-6, atol=1e-8 * scale)
 
 
+def _mp_rhs(spec, rho, y):
+    """The right-hand side written from its definition (the rate law of the
+    burn) in mpmath arithmetic; y may be complex (complex-step)."""
+    N, R = spec.n_species, spec.n_reactions
+    T = y[N]
+    t13 = mpmath.cbrt(T)
+    basis = [1, 1 / T, 1 / t13, t13, T, T * t13 * t13, mpmath.log(T)]
+    f = [mpmath.mpf(0)] * (N + 1)
+    for r in range(R):
+        lam = mpmath.exp(sum(mpmath.mpf(float(spec.coef[r, k])) * basis[k] for k in range(7)))
+        reac = [int(x) for x in spec.reactants[r] if x >= 0]
+        rate = lam * mpmath.mpf(float(rho)) ** (len(reac) - 1)
+        for sp in reac:
+            rate *= y[sp]
+        for sp in set(reac):
+            rate /= math.factorial(reac.count(sp))
+        for sp in reac:
+            f[sp] -= rate
+        for sp in spec.products[r]:
+            if sp >= 0:
+                f[int(sp)] += rate
+        f[N] += mpmath.mpf(float(spec.q[r])) * rate / mpmath.mpf(float(spec.c_v))
+    return f
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 5])
+def test_jacobian_vs_complex_step(oracle, cfg):
+    """The analytic Jacobian against the complex-step derivative of the rate
+    law evaluated in 40-digit arithmetic (step 1e-30: exact to ~1e-60), entry
+    by entry to 1e-13 of the entry's exact value."""
+    spec = synth.config(cfg, n_cells=4).networks[0]
+    net = oracle.OracleNet(spec)
+    rng = np.random.default_rng(100 + cfg)
+    n = spec.n
+    mpmath.mp.dps = 40
+    try:
+        for _ in range(2):
+            y = np.concatenate([rng.uniform(0.01, 1, spec.n_species), [rng.uniform(1.2, 4.5)]])
+            rho = 10 ** rng.uniform(0, 2)
+            J = oracle.jac(net, rho, y)
+            Jref = np.zeros((n, n))
+            for j in range(n):
+                yc = [mpmath.mpc(float(v)) for v in y]
+                yc[j] += mpmath.mpc(0, 1e-30)
+                fc = _mp_rhs(spec, rho, yc)
+                Jref[:, j] = [float(mpmath.im(v) / mpmath.mpf("1e-30")) for v in fc]
+            # each entry against its own exact value (a structural zero must
+            # come out as exactly zero)
+            rel = np.abs(J - Jref) / (np.abs(Jref) + 1e-300)
+            print(f"config {cfg}: max relative entry error {rel.max():.2e}")
+            assert rel.max() <= 1e-13, rel.max()
+    finally:
+        mpmath.mp.dps = 50
+
+
 def test_jacobian_zero_abundance_and_structure(oracle):
     """With Y_j = 0 the slot-product derivative is still right (2B->B+C at B=0
     has dR/dB = 0 but B+C->A+C has dR/dB = k rho C); zero pattern matches the

@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from tests.parity import assert_parity
+from tests.parity import ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL, assert_parity
 
 RT, AT = 1e-6, 1e-10
 
@@ -46,15 +46,27 @@ def test_divergent_cell_checked_against_tight_reference():
     g = _copy(o)
     g[3][0, 11] += 1                  # a different decision sequence
     g[0][2, 11] *= 1.0 + 5 * RT       # 5x the tolerance away from the oracle
+    m = ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL
     # no tight reference: rejected
     with pytest.raises(AssertionError):
-        assert_parity(g, o, RT, AT)
+        assert_parity(g, o, RT, AT, min_counter_equal=m)
     # the tight solution sits near the GPU result: accepted
-    assert_parity(g, o, RT, AT, tight=lambda idx: (g[0][:, idx], g[1][idx]))
+    assert_parity(g, o, RT, AT, min_counter_equal=m,
+                  tight=lambda idx: (g[0][:, idx], g[1][idx]))
     # the tight solution is far (300 tolerances) from the GPU result: rejected
     far = lambda idx: (g[0][:, idx] * (1.0 + 300 * RT), g[1][idx])  # noqa: E731
     with pytest.raises(AssertionError):
-        assert_parity(g, o, RT, AT, tight=far)
+        assert_parity(g, o, RT, AT, min_counter_equal=m, tight=far)
+
+
+def test_default_gate_allows_no_divergence_in_small_samples():
+    """The default share (99.9 %) leaves no divergent cell in a sample of
+    fewer than 1000 cells, even one that is within the tolerance."""
+    o = _case()
+    g = _copy(o)
+    g[3][0, 11] += 1
+    with pytest.raises(AssertionError):
+        assert_parity(g, o, RT, AT)
 
 
 def test_too_many_divergent_cells_fail():
