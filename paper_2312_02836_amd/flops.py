@@ -1,8 +1,26 @@
-"""Algorithmic FP64 operation count of a burn, from the per-cell counters.
+"""Algorithmic FP64 operation counts of a burn, from the per-cell counters.
 
 Every operation the method must perform is counted once: add, mul, fma (2),
 division, square root and each transcendental (exp, log, cbrt, pow) as one
-operation, whatever its cost in instructions on a given chip.  The terms:
+operation, whatever its cost in instructions on a given chip.
+
+Two models.  ``path_cell_flops`` is the one the roofline fraction uses: per
+right-hand side, Jacobian, Newton matrix and LU, solve and step attempt, the
+operations of the method's definition (n = N + 1; per reaction r: m_r
+reactant slots, u_r distinct reactant species, s_r species with nu != 0):
+
+  F_rhs   = c_T + sum_r (15 + m_r + 2 s_r)      c_T = log + cbrt + div + 4 mul
+  F_jac   = c_T + sum_r (25 + 2 u_r + 2 s_r (u_r + 1) + 2 (u_r + 1))
+  F_M     = n^2 + n                              I - cJ
+  F_LU    = n(n-1)/2 + n(n-1)(2n-1)/3
+  F_solve = 2 n^2 - n  (+ 6 n of Newton vector work per solve)
+  F_step  = (3 k + 10) n per step attempt        (k: the cell's final order)
+
+  F_cell = n_rhs F_rhs + n_jac F_jac + n_lu (F_M + F_LU)
+           + n_solve (F_solve + 6 n) + (n_steps + n_rej + n_fail) F_step
+
+``cell_flops`` is a heavier accounting of the same burn (it also counts the
+history update, the rescale and the order-choice norms), reported beside it:
 
   F_rhs    T powers (6) + per reaction r: exponent (12) + exp + multiplier +
            1/prod(m!) + rho^(n_r-1) + the n_r abundance factors + heat (2),
@@ -25,6 +43,50 @@ F_cell = n_rhs F_rhs + n_jac F_jac + n_lu F_lu + n_solve F_solve
 from __future__ import annotations
 
 import numpy as np
+
+
+def _reaction_shape(spec):
+    """Per reaction: reactant slots m_r, distinct reactant species u_r, and
+    species with a nonzero net coefficient s_r."""
+    m, u, s = [], [], []
+    for r in range(spec.n_reactions):
+        reac = [int(x) for x in spec.reactants[r] if x >= 0]
+        nu = {}
+        for x in reac:
+            nu[x] = nu.get(x, 0) - 1
+        for x in spec.products[r]:
+            if x >= 0:
+                nu[int(x)] = nu.get(int(x), 0) + 1
+        m.append(len(reac))
+        u.append(len(set(reac)))
+        s.append(sum(1 for v in nu.values() if v))
+    return np.array(m, np.int64), np.array(u, np.int64), np.array(s, np.int64)
+
+
+def path_costs(spec) -> dict:
+    """Operations per evaluation in the hot-path model (module docstring)."""
+    n = spec.n
+    m, u, s = _reaction_shape(spec)
+    c_t = 7
+    return {"rhs": c_t + int((15 + m + 2 * s).sum()),
+            "jac": c_t + int((25 + 2 * u + 2 * s * (u + 1) + 2 * (u + 1)).sum()),
+            "m": n * n + n,
+            "lu": n * (n - 1) // 2 + n * (n - 1) * (2 * n - 1) // 3,
+            "solve": 2 * n * n - n + 6 * n}
+
+
+def path_cell_flops(spec, counters: np.ndarray) -> np.ndarray:
+    """Per-cell operation count of the hot-path model; counters is [8, C]."""
+    c = np.asarray(counters, dtype=np.int64)
+    n_steps, n_rej, n_fail, n_rhs, n_jac, n_lu, n_solve, order = c[:8]
+    k = path_costs(spec)
+    n = spec.n
+    return (n_rhs * k["rhs"] + n_jac * k["jac"] + n_lu * (k["m"] + k["lu"])
+            + n_solve * k["solve"] + (n_steps + n_rej + n_fail) * (3 * order + 10) * n)
+
+
+def path_total_flops(spec, counters: np.ndarray) -> float:
+    return float(path_cell_flops(spec, counters).sum())
 
 
 def per_eval_costs(spec) -> dict:

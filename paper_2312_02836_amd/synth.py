@@ -435,6 +435,12 @@ def draw_cells(seed: int, net: NetworkSpec, n_cells: int, *,
 CONFIG_SEEDS = {1: 11, 2: 22, 3: 33, 4: 44, 5: 55}
 MIXED_SIZES = [(13, 30), (21, 60), (35, 100), (50, 150)]
 
+# Burn time of the 50/150 workload: chosen so that the 95th / 5th percentile
+# ratio of the accepted-step counts is about 10 (10.7 on a 4,096-cell sample;
+# tests/golden/calibrate_synth50_t_end.py, which calls the oracle, wrote the
+# value to tests/golden/synth50_t_end.txt).
+SYNTH50_T_END = 3e-4
+
 
 def config(i: int, n_cells: Optional[int] = None) -> BurnConfig:
     """The synthetic workloads (sizes and distributions as described in the
@@ -457,7 +463,7 @@ def config(i: int, n_cells: Optional[int] = None) -> BurnConfig:
         net = random_network(s, 50, 150)
         C = n_cells or 1048576
         cells = draw_cells(s + 1, net, C, T_range=(0.8, 6.0), T_log=True, rho_range=(1.0, 1e3))
-        return BurnConfig("synth50x150-1M", [net], [cells], t_end=1e-2)
+        return BurnConfig("synth50x150-1M", [net], [cells], t_end=SYNTH50_T_END)
     if i == 4:
         nets = [random_network(s + 10 * j, ns, nr) for j, (ns, nr) in enumerate(MIXED_SIZES)]
         C = n_cells or 65536

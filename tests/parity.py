@@ -43,13 +43,25 @@ def summary(rep) -> str:
 # lie within 100 (rtol |y| + atol) of closed forms and tight references).
 GLOBAL_ERROR_BOUND = 100.0
 
-# Share of cells that may take another decision sequence than the oracle's.
-# On networks where no one-ulp change of the oracle's own rounding flips any
-# decision (13/30, 21/60, 35/100 at rtol 1e-6), 0.1 %: in practice none.
+# Share of cells that must take the oracle's decision sequence.  On networks
+# where no one-ulp change of the oracle's own rounding flips any decision,
+# 99.9 % (in practice all).
 DEFAULT_MIN_COUNTER_EQUAL = 0.999
-# The 50-species network: one-ulp changes of the oracle's rounding flip
-# 0.6-2 % of its cells (tests/test_oracle_rounding.py), so 3 %.
-ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL = 0.97
+# Networks on which one-ulp changes of the oracle's own rounding do flip some
+# cells' decisions (tests/test_oracle_rounding.py measures every network the
+# GPU tests use): (share, cells allowed on top of the share, for samples too
+# small for the share to allow one).
+ROUNDING_SENSITIVE = {
+    "synth50x150s74": (0.97, 1),   # mixed workload's 50/150: 0.6-2 % of cells flip
+    "synth13x30s44": (0.999, 1),   # mixed workload's 13/30: 1-2 of 4,096 cells flip
+}
+ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL = ROUNDING_SENSITIVE["synth50x150s74"][0]
+
+
+def gate_for(spec) -> dict:
+    """assert_parity's decision-share arguments for a network."""
+    share, extra = ROUNDING_SENSITIVE.get(spec.name, (DEFAULT_MIN_COUNTER_EQUAL, 0))
+    return {"min_counter_equal": share, "extra_divergent": extra}
 
 # Every parity check of the session, for the end-of-run summary (conftest).
 RECORD = []

@@ -6,8 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2312_02836_amd import synth
-from tests.parity import (DEFAULT_MIN_COUNTER_EQUAL, ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL,
-                          assert_parity)
+from tests.parity import assert_parity, gate_for
 
 pytestmark = pytest.mark.gpu
 
@@ -47,8 +46,7 @@ def _run_gpu(B, spec, cells, t_end, gY, gE, log_mult=None, max_steps=2048):
 GRAD_RTOL = 1e-10
 
 
-def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rtol=GRAD_RTOL,
-                   min_counter_equal=DEFAULT_MIN_COUNTER_EQUAL, extra_divergent=0):
+def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rtol=GRAD_RTOL):
     C = cells.n_cells
     gY, gE = _cot(spec, C, seed)
     Yg, Tg, Eg, stg, cntg, gg = _run_gpu(B, spec, cells, t_end, gY, gE, log_mult)
@@ -62,7 +60,7 @@ def _check_adjoint(B, oracle, spec, cells, t_end, seed=0, log_mult=None, grad_rt
 
     # the replayed end state
     rep = assert_parity((Yg, Tg, stg, cntg), (Yo, To, sto, cnto), RTOL, ATOL, tight=tight,
-                        min_counter_equal=min_counter_equal, extra_divergent=extra_divergent)
+                        **gate_for(spec))
     assert np.allclose(Eg, spec.c_v * (Tg - cells.T), rtol=1e-12, atol=1e-14)
     # gradients where both sides replayed the same schedule
     go = oracle.vjp(onet, S, gY, gE)
@@ -98,8 +96,7 @@ def test_adjoint_synth50(gpu, oracle):
     ~6e-9 of their scale; the bound is 1e-8."""
     cfg = synth.config(4, n_cells=33)
     _check_adjoint(gpu, oracle, cfg.networks[3], cfg.cells[3], cfg.t_end, seed=2,
-                   grad_rtol=1e-8, min_counter_equal=ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL,
-                   extra_divergent=1)
+                   grad_rtol=1e-8)
 
 
 def test_adjoint_bateman_chain(gpu, oracle):

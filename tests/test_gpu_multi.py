@@ -5,14 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2312_02836_amd import synth
-from tests.parity import (DEFAULT_MIN_COUNTER_EQUAL, ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL,
-                          assert_parity)
-
-
-def _min_equal(spec):
-    """The 50-species network is rounding-sensitive (tests/test_oracle_rounding.py)."""
-    return (ROUNDING_SENSITIVE_MIN_COUNTER_EQUAL if spec.n_species >= 50
-            else DEFAULT_MIN_COUNTER_EQUAL)
+from tests.parity import assert_parity, gate_for
 
 pytestmark = pytest.mark.gpu
 
@@ -38,7 +31,7 @@ def _oracle(oracle, spec, cells, t_end, **kw):
     return oracle.burn(oracle.OracleNet(spec), cells, t_end, RTOL, ATOL, **kw)
 
 
-def _check(g, oracle, spec, cells, t_end, min_counter_equal=DEFAULT_MIN_COUNTER_EQUAL):
+def _check(g, oracle, spec, cells, t_end):
     """Parity with the oracle on the same cells (tests.parity.assert_parity);
     counter-divergent cells are checked against a 1e4 times tighter oracle
     solution."""
@@ -48,7 +41,7 @@ def _check(g, oracle, spec, cells, t_end, min_counter_equal=DEFAULT_MIN_COUNTER_
         r = oracle.burn(oracle.OracleNet(spec), cells.subset(idx), t_end, RTOL * 1e-4, ATOL * 1e-4)
         return r[0], r[1]
 
-    return assert_parity(g, o, RTOL, ATOL, min_counter_equal=min_counter_equal, tight=tight)
+    return assert_parity(g, o, RTOL, ATOL, tight=tight, **gate_for(spec))
 
 
 def _mixed(n_cells=(700, 513, 300, 257)):
@@ -81,7 +74,7 @@ def test_plain_large_networks(gpu, oracle, which):
     net = gpu.Network(spec)
     print("launch", net.get_launch(), flush=True)
     g = _host(gpu.burn(net, c.Y, c.rho, c.T, cfg.t_end, RTOL, ATOL))
-    _check(g, oracle, spec, c, cfg.t_end, min_counter_equal=_min_equal(spec))
+    _check(g, oracle, spec, c, cfg.t_end)
     net.close()
 
 
@@ -96,8 +89,7 @@ def test_multi_mixed_parity_and_bitwise_plain(gpu, oracle):
     for n, spec, c, out in zip(nets, cfg.networks, cells, outs):
         g = _host(out)
         print(spec.name, flush=True)
-        _check(g, oracle, spec, c, cfg.t_end,
-               min_counter_equal=_min_equal(spec))
+        _check(g, oracle, spec, c, cfg.t_end)
     for n, spec in zip(nets, cfg.networks):
         n.set_launch(32 if spec.n <= 32 else 64, 1, 0)
     outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cells)], cfg.t_end,
@@ -218,14 +210,13 @@ def test_every_plain_shape_via_set_launch(gpu, oracle):
     net.close()
 
 
-def _sampled(oracle, spec, cells, t_end, out, n_sample, seed,
-             min_counter_equal=DEFAULT_MIN_COUNTER_EQUAL):
+def _sampled(oracle, spec, cells, t_end, out, n_sample, seed):
     g = _host(out)
     idx = np.sort(np.random.default_rng(seed).choice(cells.n_cells, n_sample, replace=False))
     sub = cells.subset(idx)
     gs = (g[0][:, idx], g[1][idx], g[2][idx], g[3][:, idx])
     print(spec.name, "sample", n_sample, "of", cells.n_cells, flush=True)
-    _check(gs, oracle, spec, sub, t_end, min_counter_equal=min_counter_equal)
+    _check(gs, oracle, spec, sub, t_end)
     assert np.all(g[2] == 0)
 
 
@@ -279,8 +270,7 @@ def test_mixed4_full_size_sampled(gpu, oracle):
     outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cfg.cells)], cfg.t_end,
                           RTOL, ATOL)
     for i, (spec, c, out) in enumerate(zip(cfg.networks, cfg.cells, outs)):
-        _sampled(oracle, spec, c, cfg.t_end, out, 384, i,
-                 min_counter_equal=_min_equal(spec))
+        _sampled(oracle, spec, c, cfg.t_end, out, 384, i)
     for n in nets:
         n.close()
 
@@ -294,5 +284,5 @@ def test_synth50_full_size_sampled(gpu, oracle):
     assert cells.n_cells == 1048576
     net = gpu.Network(spec)
     out = gpu.burn_multi([(net, cells.Y, cells.rho, cells.T)], cfg.t_end, RTOL, ATOL)[0]
-    _sampled(oracle, spec, cells, cfg.t_end, out, 256, 7, min_counter_equal=_min_equal(spec))
+    _sampled(oracle, spec, cells, cfg.t_end, out, 256, 7)
     net.close()

@@ -13,13 +13,16 @@ necessarily round differently from the oracle (their exp, cbrt and log are
 other implementations; they fuse multiply-adds), so the fractions measured
 here bound what the GPU parity tests can demand:
 
-  * 13/30, 21/60, 35/100 networks: no perturbation changes any cell's
-    decisions -> the GPU must take the oracle's decisions on >= 99.9 % of
-    the cells;
-  * 50/150 network: every perturbation changes the decisions of 0.5-2 % of
-    the cells, and those cells end up to several tolerances apart -> the GPU
-    gate allows 3 % of the cells to diverge, each within the global-error
-    bound of a tight reference.
+  * most networks: no perturbation changes any cell's decisions -> the GPU
+    must take the oracle's decisions on >= 99.9 % of the cells;
+  * the mixed workload's 50/150 network: every perturbation changes the
+    decisions of 0.5-2 % of the cells, and those cells end up to several
+    tolerances apart -> the GPU gate allows 3 % of its cells to diverge,
+    each within the global-error bound of a tight reference;
+  * the mixed workload's 13/30 network: 1-2 cells in 4,096 flip -> one
+    divergent cell is allowed in samples too small for 0.1 % to allow one.
+The gate's table (tests/parity.py: ROUNDING_SENSITIVE) is checked against
+these measurements network by network.
 """
 import numpy as np
 import pytest
@@ -46,18 +49,32 @@ def _self_divergence(oracle, spec, cells, t_end, rtol=RTOL, atol=ATOL):
     return out
 
 
-@pytest.mark.parametrize("cfg_i,which,n", [(2, 0, 512), (4, 1, 256), (4, 2, 256)])
-def test_networks_without_rounding_sensitivity(oracle, cfg_i, which, n):
+# every network the GPU parity tests use: (config, network index, cells)
+NETWORKS = [(1, 0, 256), (2, 0, 2048), (3, 0, 1024), (4, 0, 4096), (4, 1, 512), (4, 2, 512),
+            (4, 3, 512), (5, 0, 1024)]
+
+
+@pytest.mark.parametrize("cfg_i,which,n", NETWORKS)
+def test_gate_allowances_match_measured_sensitivity(oracle, cfg_i, which, n):
+    """A network the gate lists as rounding-sensitive must flip some cells
+    under the probes, and no more than the share the gate requires; any
+    other network must flip none."""
+    from tests.parity import ROUNDING_SENSITIVE
     cfg = synth.config(cfg_i, n_cells=n)
-    res = _self_divergence(oracle, cfg.networks[which], cfg.cells[which], cfg.t_end)
-    for probe, (eq, ewt_same, ewt_all, _) in res.items():
-        assert eq == 1.0, (probe, eq)
-        assert ewt_all < 1e-2
+    spec = cfg.networks[which]
+    res = _self_divergence(oracle, spec, cfg.cells[which], cfg.t_end)
+    worst = min(eq for eq, _, _, _ in res.values())
+    if spec.name in ROUNDING_SENSITIVE:
+        assert ROUNDING_SENSITIVE[spec.name][0] <= worst < 1.0, (spec.name, worst)
+    else:
+        assert worst == 1.0, (spec.name, worst)
+        assert max(e for _, _, e, _ in res.values()) < 1e-2
 
 
-def test_50_species_network_is_rounding_sensitive(oracle):
-    """On the 50/150 network a one-ulp change flips decisions on 0.5-2 % of
-    the cells; the flipped cells stay valid solutions: within the oracle's
+def test_50_species_network_flips_stay_valid(oracle):
+    """On the mixed workload's 50/150 network a one-ulp change flips
+    decisions on 0.5-2 % of the cells; the flipped cells stay valid
+    solutions: within the oracle's
     pinned global-error bound (100 tolerances) of a solution at a 1e4 times
     tighter tolerance."""
     cfg = synth.config(4, n_cells=512)

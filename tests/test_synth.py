@@ -113,3 +113,13 @@ def test_networks_react_from_seed_composition(i):
         k = sum(all(s in seeds for s in net.reactants[r] if s >= 0)
                 for r in range(net.n_reactions))
         assert k >= 3, (net.name, k)
+
+
+def test_synth50_t_end_is_the_calibrated_value():
+    """The 50/150 workload's burn time is the one the committed calibration
+    (the oracle's step-count spread on 4,096 cells) chose."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "synth50_t_end.txt")
+    with open(path) as f:
+        val = [float(l.split("=")[1]) for l in f if l.startswith("t_end =")][0]
+    assert synth.config(3, n_cells=8).t_end == val == synth.SYNTH50_T_END
