@@ -222,6 +222,26 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
                      double atol, const bn_burn_opts *opts, void *workspace,
                      size_t workspace_bytes, void *stream);
 
+/* Bytes of device scratch burn_batch_multi_noalloc has on each device. */
+#define BN_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* burn_batch_multi for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments and results as burn_batch_multi, without the workspace:
+ * the queue counters and (order_cells = 1) the order and staging arrays live
+ * in a static device array of BN_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on every device it runs on until the process ends.  The call itself
+ * allocates nothing (no hipMalloc, no library allocation); its counters are
+ * cleared by kernels at the start of every call.  Calls on one device share
+ * that array: two calls in flight on the same device at once (on different
+ * streams, or from different threads without ordering) race and their results
+ * are undefined.  A launch that needs more scratch than the array holds
+ * (burn_batch_multi_order_workspace_bytes, or burn_batch_multi_workspace_bytes
+ * without ordering) is rejected with BN_EINVAL and a message naming both
+ * sizes; nothing is enqueued.  Returns BN_SUCCESS or a negative code. */
+int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double dt,
+                             double rtol, double atol, const bn_burn_opts *opts, void *stream);
+
 /* ---- Launch-shape autotuner -------------------------------------------- */
 
 typedef struct {

@@ -22,7 +22,7 @@ COUNTERS = ["n_steps", "n_rej_err", "n_newton_fail", "n_rhs", "n_jac", "n_lu", "
 EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "bn_network_n_reactions", "burn_batch", "burn_batch_ex",
            "burn_batch_multi_workspace_bytes", "burn_batch_multi_order_workspace_bytes",
-           "burn_batch_multi", "bn_network_autotune",
+           "burn_batch_multi", "burn_batch_multi_noalloc", "bn_network_autotune",
            "bn_network_set_launch", "bn_network_get_launch",
            "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
            "burn_batch_adjoint_backward", "burn_batch_adjoint", "burn_batch_sdc",
@@ -88,6 +88,9 @@ def lib() -> C.CDLL:
     L.burn_batch_multi.argtypes = [C.c_int32, C.POINTER(BatchItem), C.c_double, C.c_double,
                                    C.c_double, C.POINTER(BurnOpts), vp, C.c_size_t, vp]
     L.burn_batch_multi.restype = C.c_int
+    L.burn_batch_multi_noalloc.argtypes = [C.c_int32, C.POINTER(BatchItem), C.c_double,
+                                           C.c_double, C.c_double, C.POINTER(BurnOpts), vp]
+    L.burn_batch_multi_noalloc.restype = C.c_int
     L.bn_network_autotune.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
                                       C.c_double, dp, C.c_int32, C.POINTER(TuneResult),
                                       C.c_int32, C.POINTER(C.c_int32), vp]

@@ -458,10 +458,14 @@ size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_it
   return s;
 }
 
-int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, double rtol,
-                     double atol, const bn_burn_opts *opts, void *workspace,
-                     size_t workspace_bytes, void *stream) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+
+// burn_batch_multi with the workspace given (the caller's, or the library's
+// static scratch for burn_batch_multi_noalloc).
+int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rtol, double atol,
+               const bn_burn_opts *opts, void *workspace, size_t workspace_bytes, void *stream) {
   if (n_items < 0 || n_items > BN_MAX_ITEMS)
     return fail(BN_EINVAL, "n_items must be 0..BN_MAX_ITEMS");
   if (n_items > 0 && !items) return fail(BN_EINVAL, "null items");
@@ -637,6 +641,42 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
     }
   }
   return BN_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, double rtol,
+                     double atol, const bn_burn_opts *opts, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+  g_err.clear();
+  return multi_impl(n_items, items, dt, rtol, atol, opts, workspace, workspace_bytes, stream);
+}
+
+int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double dt,
+                             double rtol, double atol, const bn_burn_opts *opts, void *stream) {
+  g_err.clear();
+  if (n_items < 0 || n_items > BN_MAX_ITEMS)
+    return fail(BN_EINVAL, "n_items must be 0..BN_MAX_ITEMS");
+  if (n_items > 0 && !items) return fail(BN_EINVAL, "null items");
+  for (int j = 0; j < n_items; ++j)
+    if (!items[j].net) return fail(BN_EINVAL, "null network in item " + std::to_string(j));
+  const bool ordered = opts && opts->order_cells == 1;
+  const size_t need = ordered ? burn_batch_multi_order_workspace_bytes(n_items, items)
+                              : burn_batch_multi_workspace_bytes(n_items);
+  if (need > (size_t)BN_NOALLOC_SCRATCH_BYTES)
+    return fail(BN_EINVAL, "burn_batch_multi_noalloc: the launch needs " + std::to_string(need) +
+                               " bytes of scratch, the library's static scratch holds " +
+                               std::to_string((size_t)BN_NOALLOC_SCRATCH_BYTES) +
+                               " (use burn_batch_multi with a workspace)");
+  void *scratch = nullptr;
+  const hipError_t e = bn::noalloc_scratch(&scratch);
+  if (e != hipSuccess)
+    return fail(BN_EHIP, std::string("hipGetSymbolAddress of the static scratch failed: ") +
+                             hipGetErrorString(e));
+  return multi_impl(n_items, items, dt, rtol, atol, opts, scratch,
+                    (size_t)BN_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int bn_network_set_launch(bn_network *net, int32_t lanes_per_cell, int32_t slots_per_lane,

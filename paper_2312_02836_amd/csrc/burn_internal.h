@@ -109,6 +109,11 @@ struct MultiArgs {
 };
 hipError_t launch_multi(const MultiArgs &m, int grid, int W, hipStream_t stream);
 
+// Device address of the current device's copy of the static scratch array
+// (BN_NOALLOC_SCRATCH_BYTES bytes, 256-byte aligned) that
+// burn_batch_multi_noalloc uses as its workspace; looked up once per device.
+hipError_t noalloc_scratch(void **out);
+
 // Queue order of one item of the persistent kernel, costliest cells first:
 // a probe launch computes every cell's initial step size h0 (one right-hand
 // side), then a counting sort over ORDER_BUCKETS buckets of log2 h0 gives

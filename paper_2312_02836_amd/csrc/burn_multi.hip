@@ -25,7 +25,43 @@
 
 #include "burn_body.h"
 
+#include <mutex>
+
+#include "burn.h"
+
 namespace bn {
+
+// The workspace of burn_batch_multi_noalloc (queue counters and, for ordered
+// launches, the cost-order keys, positions and staged cell arrays).  Every
+// device the library runs on holds its own copy until the process ends; the
+// calls on one device share it (they must not overlap).  Host code never
+// uses this name as an address: noalloc_scratch() looks the device address
+// up once per device.
+static __device__ __align__(256) unsigned char scratch[BN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void **out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_plain_p0(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream,
                            bool *found);
