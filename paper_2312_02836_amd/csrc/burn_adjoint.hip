@@ -21,14 +21,15 @@
 // dL/dp_r (W = nu for a species, q_r / c_v for temperature), then the
 // transposes of the predictor, psi and the rescale.
 //
-// Memory: the schedule and a checkpoint of D every CK steps live in a
-// caller-provided workspace; the reverse sweep recomputes each CK-step
-// segment forward from its checkpoint, keeping the corrected states of the
-// segment in LDS, and walks it backwards.
+// Memory: the schedule, a checkpoint of D every CK steps and the corrected
+// states of one CK-step segment live in a caller-provided workspace; the
+// reverse sweep recomputes each segment forward from its checkpoint, keeping
+// its corrected states, and walks it backwards.
 //
-// Mapping: one cell per wave, lane i = component i (n <= 64); the Newton
-// matrix sits in LDS, one row per lane, and is factored there with
-// row-position tracking; reactions are spread over the lanes.
+// Mapping: a cell per group of 32 lanes (two per wave) for systems of up to
+// 32 components, else a whole wave; lane i of the group = component i.  The
+// Newton matrix sits in LDS, one row per lane, and is factored there with
+// row-position tracking; reactions are spread over the group's lanes.
 
 #include "burn_body.h"
 
@@ -61,11 +62,49 @@ burn_record_kernel(BurnArgs a, int block_waves) {
 
 // ---------------------------------------------------------------------------
 // Replay / adjoint kernel.
+//
+// A cell is owned by a group of G lanes, lane i of the group holding
+// component i: G = 32 for systems of up to 32 components (two cells per
+// wave), else 64.  The cells of a wave keep their own schedules: every loop
+// over segments, steps and Newton iterations runs to the largest count among
+// the wave's cells, each cell working only while its own count lasts, and
+// every cross-lane operation stays inside a group.
 
-// LDS doubles per wave for a system of size n.
-__host__ __device__ inline size_t adj_wave_doubles(int n) {
-  const int ms = n | 1;
-  return 64 * 6 + (size_t)n * ms + (size_t)CK * n;
+// Per-cell LDS: six n-vectors (state, right-hand side accumulator, solve
+// vector, J^T mu accumulator, reciprocal pivots, pivot rows), the Newton
+// matrix (n rows, odd stride n | 1) and the gradient accumulators (R).  The
+// corrected states of the segment being reversed live in the workspace
+// (AdjArgs::seg).
+__host__ __device__ inline int adj_vec_stride(int n) { return (n + 1) & ~1; }
+__host__ __device__ inline size_t adj_cell_doubles(int n, int R) {
+  return 6 * (size_t)adj_vec_stride(n) + (size_t)n * (size_t)(n | 1) + (size_t)((R + 1) & ~1);
+}
+__host__ __device__ inline int adj_group(int n) { return n <= 32 ? 32 : 64; }
+__host__ __device__ inline size_t adj_wave_doubles(int n, int R) {
+  return (size_t)(64 / adj_group(n)) * adj_cell_doubles(n, R);
+}
+
+// Component k (wave-uniform) of the lane's group.
+template <int G>
+__device__ __forceinline__ double group_read(double v, int k) {
+  if constexpr (G == 64) {
+    return readlane_f64(v, k);
+  } else {
+    static_assert(G == 32, "groups of 32 or 64 lanes");
+    const double lo = readlane_f64(v, k), hi = readlane_f64(v, k + 32);
+    return (threadIdx.x & 32) ? hi : lo;
+  }
+}
+
+// Largest of a group-uniform value over the wave's groups.
+template <int G>
+__device__ __forceinline__ int wave_max_of_groups(int v) {
+  int m = __builtin_amdgcn_readlane(v, 0);
+  if constexpr (G == 32) {
+    const int b = __builtin_amdgcn_readlane(v, 32);
+    m = b > m ? b : m;
+  }
+  return m;
 }
 
 // Rate of reaction r at the state in ybuf (T-powers given) and its
@@ -130,13 +169,14 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-// One cell per wave.  BACKWARD = false: replay from y(0), write the
-// checkpoints, the end state and E.  BACKWARD = true: reverse sweep.  W is
-// the waves per SIMD the registers are budgeted for (3 when the LDS lets
-// three waves per SIMD reside, else 2).
-template <bool BACKWARD, int W>
+// BACKWARD = false: replay from y(0), write the checkpoints, the end state
+// and E.  BACKWARD = true: reverse sweep.  W is the waves per SIMD the
+// registers are budgeted for (3 when the LDS lets three waves per SIMD
+// reside, else 2); G the lanes per cell.
+template <bool BACKWARD, int W, int G>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
 adjoint_kernel(AdjArgs a) {
+  constexpr int CPW = 64 / G;   // cells per wave
   extern __shared__ double smem[];
   load_tables(a.net, a.log_mult, smem);
   __syncthreads();
@@ -144,62 +184,77 @@ adjoint_kernel(AdjArgs a) {
   const NetTables &nt = a.net;
   const int N = nt.N, R = nt.R, n = nt.n;
   const int ne = nt.max_ent;  // entries per reaction, padded (ent_of)
-  const int MS = n | 1;
+  const int MS = n | 1, VS = adj_vec_stride(n);
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t cell = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
-  if (cell >= a.n_cells) return;  // whole wave: no later workgroup barrier
-
-  double *wb = smem + tab_doubles_of(R) + (size_t)wave * adj_wave_doubles(n);
-  double *ybuf = wb;
-  double *facc = wb + 64;
-  double *vbuf = wb + 128;
-  double *jout = wb + 192;
-  double *dinvp = wb + 256;
-  int *prow = reinterpret_cast<int *>(wb + 320);
-  double *M = wb + 384;
-  double *seg = M + (size_t)n * MS;
-
+  const int cs = lane / G;  // the lane's cell slot in the wave
+  const int i = lane % G;   // the lane's component
   const int64_t C = a.n_cells;
-  const bool own = lane < n;  // lane owns component `lane`
+  const int64_t first = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * CPW;
+  if (first >= C) return;  // whole wave: no later workgroup barrier
+  const bool valid = first + cs < C;
+  const int64_t cell = valid ? first + cs : C - 1;  // an empty slot reads a real cell
+
+  double *wb = smem + tab_doubles_of(R) + (size_t)wave * adj_wave_doubles(n, R) +
+               (size_t)cs * adj_cell_doubles(n, R);
+  double *ybuf = wb;
+  double *facc = wb + VS;
+  double *vbuf = wb + 2 * VS;
+  double *jout = wb + 3 * VS;
+  double *dinvp = wb + 4 * VS;
+  int *prow = reinterpret_cast<int *>(wb + 5 * VS);
+  double *M = wb + 6 * VS;
+  double *grl = M + (size_t)n * MS;  // gradient accumulators, reaction r on lane r % G
+
+  const bool own = i < n;  // lane owns component i
   const double rho = a.rho[cell];
   const double *blk = a.sched + cell * a.sched_stride;
-  const int n_steps = (int)blk[0];
+  const int n_rec = (int)blk[0];
   const double *sh = blk + 2;
   const double *sr = blk + 2 + a.sched_cap;
   const int32_t *so = reinterpret_cast<const int32_t *>(blk + 2 + 2 * (int64_t)a.sched_cap);
   double *ck = a.ckpt + (size_t)cell * a.n_ckpt * 7 * n;
 
+  // every slot starts with a valid pivot order and a finite state, so that
+  // the group operations a resting cell takes part in stay in bounds
+  if (own) {
+    prow[i] = i;
+    dinvp[i] = 1.0;
+    ybuf[i] = 1.0;
+  }
+
   // a failed recording run (or, backward, a failed replay): no replay
   const int st_in = a.status[cell];
-  if (n_steps < 0 || st_in != ST_OK) {
+  const bool dead = !valid || n_rec < 0 || st_in != ST_OK;
+  if (dead && valid) {
     if constexpr (BACKWARD) {
-      for (int r = lane; r < R; r += 64) a.grad[(int64_t)r * C + cell] = 0.0;
+      for (int r = i; r < R; r += G) a.grad[(int64_t)r * C + cell] = 0.0;
     } else {
-      if (lane == 0) {
+      if (i == 0) {
         a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
         if (a.iters) a.iters[cell] = a.iters[C + cell] = 0;
       }
     }
-    return;
   }
+  const int nst = dead ? 0 : n_rec;  // this cell's accepted steps
 
   // initial state
   double y0v = 0.0;
-  if (own) y0v = (lane < N) ? a.Y0[(int64_t)lane * C + cell] : a.T0[cell];
+  if (own) y0v = (i < N) ? a.Y0[(int64_t)i * C + cell] : a.T0[cell];
 
-  // ---- wave-level building blocks ----
-  // F = f(y) into facc (species rows) + heat; the Newton matrix I - cJ(y)
-  // into M.  y is taken from ybuf.  Returns 1 if everything is finite.
+  // ---- group building blocks ----
+  // F = f(y) (component i) for cells with want_f; the Newton matrix I - cJ(y)
+  // into M for cells with want_m.  y is taken from ybuf.  Returns 1 if
+  // everything evaluated is finite.
   auto eval_f_m = [&](double c, bool want_f, bool want_m, double &f_out) -> int {
-    if (want_f && own) facc[lane] = 0.0;
+    if (want_f && own) facc[i] = 0.0;
     if (want_m && own)
-      for (int j = 0; j < n; ++j) M[lane * MS + j] = (lane == j) ? 1.0 : 0.0;
+      for (int j = 0; j < n; ++j) M[i * MS + j] = (i == j) ? 1.0 : 0.0;
     wave_lds_sync();
     const TPow tp = tpow(ybuf[N]);
     double heat = 0.0;
     int bad = 0;
-    for (int r = lane; r < R; r += 64) {
+    for (int r = i; r < R; r += G) {
       double g[4];
       const double v = rate_and_slots(tb, r, tp, ybuf, rho, want_m, g);
       const int4 *ro = reinterpret_cast<const int4 *>(tb.rout + 8 * r);
@@ -231,21 +286,22 @@ adjoint_kernel(AdjArgs a) {
         }
       }
     }
-    heat = gsum<64>(heat);
+    heat = gsum<G>(heat);
     wave_lds_sync();
     f_out = 0.0;
-    if (want_f && own) f_out = (lane < N) ? facc[lane] : heat * nt.inv_cv;
+    if (want_f && own) f_out = (i < N) ? facc[i] : heat * nt.inv_cv;
     if (own && !isfinite(f_out)) bad = 1;
-    return !gor<64>(bad);
+    return !gor<G>(bad);
   };
 
-  // LU of M in place (rows stay put; prow[p] = physical row at position p,
-  // dinvp[p] = 1/U_pp).  Returns 1 if nonsingular.
-  auto factor = [&]() -> int {
-    int pos = lane;
+  // LU of M in place for cells with do_f (rows stay put; prow[p] = physical
+  // row at position p, dinvp[p] = 1/U_pp).  Every lane takes part in the
+  // pivot searches.  Returns 1 if nonsingular.
+  auto factor = [&](bool do_f) -> int {
+    int pos = i;
     int sing = 0;
     double fdinv = 1.0;
-    double *Mrow = M + (own ? lane : 0) * MS;
+    double *Mrow = M + (own ? i : 0) * MS;
     for (int K = 0; K < n; ++K) {
       double v = -2.0;
       int nan_k = 0;
@@ -257,10 +313,10 @@ adjoint_kernel(AdjArgs a) {
           v = -1.0;
         }
       }
-      int key = cand ? ((pos << 8) | lane) : 0x7fffffff;
-      gargmax_key<64>(v, key);
+      int key = cand ? ((pos << 8) | i) : 0x7fffffff;
+      gargmax_key<G>(v, key);
       const int bp = key >> 8, prow_i = key & 255;
-      nan_k = gor<64>(nan_k);
+      nan_k = gor<G>(nan_k);
       if (!(v > 0.0) || nan_k) sing = 1;
       if (own) {
         if (pos == K) pos = bp;
@@ -269,7 +325,7 @@ adjoint_kernel(AdjArgs a) {
       const double *P = M + prow_i * MS;
       const double rinv = 1.0 / P[K];
       if (own && pos == K) fdinv = rinv;
-      if (own && pos > K) {
+      if (do_f && own && pos > K) {
         const double l = Mrow[K] * rinv;
         Mrow[K] = l;
         // whole chunks of 4 columns (loads issued together), then the rest
@@ -291,62 +347,62 @@ adjoint_kernel(AdjArgs a) {
       }
       wave_lds_sync();
     }
-    if (own) {
-      prow[pos] = lane;
+    if (do_f && own) {
+      prow[pos] = i;
       dinvp[pos] = fdinv;
     }
     wave_lds_sync();
     return !sing;
   };
 
-  // x = M^-1 b (b, x: component `lane`)
+  // x = M^-1 b (b, x: component i)
   auto solve = [&](double b) -> double {
-    if (own) vbuf[lane] = b;
+    if (own) vbuf[i] = b;
     wave_lds_sync();
-    const int pr = own ? prow[lane] : 0;  // lane works on position `lane`
+    const int pr = own ? prow[i] : 0;  // lane works on position i
     double z = own ? vbuf[pr] : 0.0;
     const double *Lrow = M + pr * MS;
     for (int K = 0; K < n; ++K) {
-      const double zk = readlane_f64(z, K);
-      if (own && lane > K) z -= Lrow[K] * zk;
+      const double zk = group_read<G>(z, K);
+      if (own && i > K) z -= Lrow[K] * zk;
     }
-    const double dv = own ? dinvp[lane] : 1.0;
+    const double dv = own ? dinvp[i] : 1.0;
     for (int K = n - 1; K >= 0; --K) {
-      const double xk = readlane_f64(z * dv, K);
-      if (lane == K) z = xk;
-      if (own && lane < K) z -= Lrow[K] * xk;
+      const double xk = group_read<G>(z * dv, K);
+      if (i == K) z = xk;
+      if (own && i < K) z -= Lrow[K] * xk;
     }
     wave_lds_sync();
-    return z;  // position `lane` = column `lane`
+    return z;  // position i = column i
   };
 
-  // y = M^-T c (c, y: component `lane`)
+  // y = M^-T c (c, y: component i)
   auto solve_t = [&](double cv) -> double {
     // U^T w = c over positions (lane p holds w_p), then L^T v = w, y = P^T v
     double w = own ? cv : 0.0;
     double acc = 0.0;
     for (int K = 0; K < n; ++K) {
-      const double wk = readlane_f64((w - acc) * (own ? dinvp[lane] : 1.0), K);
-      if (lane == K) w = wk;
+      const double wk = group_read<G>((w - acc) * (own ? dinvp[i] : 1.0), K);
+      if (i == K) w = wk;
       const int rk = prow[K];
-      if (own && lane > K) acc += M[rk * MS + lane] * wk;
+      if (own && i > K) acc += M[rk * MS + i] * wk;
     }
     double v = w;
     for (int K = n - 1; K >= 0; --K) {
-      const double vk = readlane_f64(v, K);
+      const double vk = group_read<G>(v, K);
       const int rk = prow[K];
-      if (own && lane < K) v -= M[rk * MS + lane] * vk;
+      if (own && i < K) v -= M[rk * MS + i] * vk;
     }
-    if (own) vbuf[prow[lane]] = v;
+    if (own) vbuf[prow[i]] = v;
     wave_lds_sync();
-    const double y = own ? vbuf[lane] : 0.0;
+    const double y = own ? vbuf[i] : 0.0;
     wave_lds_sync();
     return y;
   };
 
   auto wrms = [&](double v, double inv) -> double {
     const double z = own ? v * inv : 0.0;
-    return sqrt(gsum<64>(z * z) / (double)n);
+    return sqrt(gsum<G>(z * z) / (double)n);
   };
 
   // history rows of this lane's component
@@ -377,17 +433,18 @@ adjoint_kernel(AdjArgs a) {
     }
   };
 
-  // the replay of one accepted step; returns the corrected state in y_new
-  // (this lane's component); 0 on a non-finite or singular corrector.  The
-  // corrector equation is solved to ADJ_TOL; the iteration keeps the Newton
-  // matrix of the predictor while the increments shrink at least
-  // kChordRate-fold per iteration and takes a new one (a Newton step) when
-  // they do not, so its solution is the exact corrector either way.
+  // The replay of accepted step m for a cell with act (the others rest);
+  // returns the corrected state in y_new (this lane's component) and 0 on a
+  // non-finite or singular corrector.  The corrector equation is solved to
+  // ADJ_TOL; the iteration keeps the Newton matrix of the predictor while the
+  // increments shrink at least kChordRate-fold per iteration and takes a new
+  // one (a Newton step) when they do not, so its solution is the exact
+  // corrector either way.
   int n_it = 0, n_lu = 0;  // Newton iterations and factorizations of the replay
-  auto replay_step = [&](int m, double &y_new) -> int {
-    const int k = so[m];
-    const double hstep = sh[m], ratio = sr[m];
-    if (ratio != 1.0) rescale_fwd(k, ratio);
+  auto replay_step = [&](int m, bool act, double &y_new) -> int {
+    const int k = act ? so[m] : 1;
+    const double hstep = act ? sh[m] : 0.0, ratio = act ? sr[m] : 1.0;
+    if (act && ratio != 1.0) rescale_fwd(k, ratio);
     double gk = 1.0;
 #pragma unroll
     for (int kk = 1; kk <= KMAX; ++kk)
@@ -404,40 +461,53 @@ adjoint_kernel(AdjArgs a) {
     const double c = hstep / gk;
     double d = 0.0, y = ypred, dprev = 0.0;
     int ok = 1, fresh = 1;
+    bool done = !act;
     for (int it = 0; it < ADJ_MAXIT; ++it) {
-      ++n_it;
-      if (own) ybuf[lane] = y;
+      if (__ballot(!done) == 0) break;  // every cell of the wave is done
+      if (!done) ++n_it;
+      if (own && !done) ybuf[i] = y;
       double F;
-      ok = eval_f_m(c, true, fresh != 0, F);
-      if (!ok) break;
-      if (fresh) {
-        ++n_lu;
-        if (!factor()) {
-          ok = 0;
-          break;
-        }
+      const int okf = eval_f_m(c, !done, !done && fresh, F);
+      if (!done && !okf) {
+        ok = 0;
+        done = true;
+      }
+      const bool do_fac = !done && fresh;
+      if (do_fac) ++n_lu;
+      const int nonsing = factor(do_fac);
+      if (do_fac && !nonsing) {
+        ok = 0;
+        done = true;
       }
       const double dy = solve(c * F - psi - d);
       const double dn = wrms(dy, isc);
-      if (!isfinite(dn)) {
-        ok = 0;
-        break;
+      if (!done) {
+        if (!isfinite(dn)) {
+          ok = 0;
+          done = true;
+        } else {
+          y += dy;
+          d += dy;
+          if (dn <= ADJ_TOL) {
+            done = true;
+          } else {
+            fresh = it > 0 && dn > kChordRate * dprev;
+            dprev = dn;
+          }
+        }
       }
-      y += dy;
-      d += dy;
-      if (dn <= ADJ_TOL) break;
-      fresh = it > 0 && dn > kChordRate * dprev;
-      dprev = dn;
     }
     y_new = y;
     // history update (row k+2 of the production integrator only feeds its
     // error estimates, never the solution, so the replay does not keep it)
+    if (act) {
 #pragma unroll
-    for (int kk = 1; kk <= KMAX; ++kk) {
-      if (kk == k) {
-        D[kk + 1] = d;
+      for (int kk = 1; kk <= KMAX; ++kk) {
+        if (kk == k) {
+          D[kk + 1] = d;
 #pragma unroll
-        for (int j = kk; j >= 0; --j) D[j] += D[j + 1];
+          for (int j = kk; j >= 0; --j) D[j] += D[j + 1];
+        }
       }
     }
     return ok;
@@ -445,7 +515,7 @@ adjoint_kernel(AdjArgs a) {
 
   // ---------------- forward replay from y(0) ----------------
   auto init_history = [&]() -> int {
-    if (own) ybuf[lane] = y0v;
+    if (own) ybuf[i] = y0v;
     double f0;
     const int ok = eval_f_m(0.0, true, false, f0);
 #pragma unroll
@@ -457,32 +527,36 @@ adjoint_kernel(AdjArgs a) {
 
   if constexpr (!BACKWARD) {
     int ok = init_history();
+    const int m_end = wave_max_of_groups<G>(nst);
     double y_new = 0.0;
-    for (int m = 0; m < n_steps && ok; ++m) {
-      if (m % CK == 0 && own) {
+    for (int m = 0; m < m_end; ++m) {
+      const bool act = ok && m < nst;
+      if (act && m % CK == 0 && own) {
         double *cp = ck + (size_t)(m / CK) * 7 * n;
 #pragma unroll
-        for (int j = 0; j < DROWS; ++j) cp[j * n + lane] = D[j];
+        for (int j = 0; j < DROWS; ++j) cp[j * n + i] = D[j];
       }
-      ok = replay_step(m, y_new);
+      const int okm = replay_step(m, act, y_new);
+      if (act && !okm) ok = 0;
     }
-    if (lane == 0 && a.iters) {
-      a.iters[cell] = n_it;
-      a.iters[C + cell] = n_lu;
-    }
-    if (!ok) {
-      // the outputs keep the recording run's end state; E follows it
-      if (lane == 0) {
-        a.status[cell] = ST_NONFINITE;
-        a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
+    if (!dead) {
+      if (i == 0 && a.iters) {
+        a.iters[cell] = n_it;
+        a.iters[C + cell] = n_lu;
       }
-      return;
-    }
-    if (own) {
-      if (lane < N) a.Yout[(int64_t)lane * C + cell] = D[0];
-      else {
-        a.Tout[cell] = D[0];
-        a.Eout[cell] = (D[0] - y0v) / nt.inv_cv;
+      if (!ok) {
+        // the outputs keep the recording run's end state; E follows it
+        if (i == 0) {
+          a.status[cell] = ST_NONFINITE;
+          a.Eout[cell] = (a.Tout[cell] - a.T0[cell]) / nt.inv_cv;
+        }
+      } else if (own) {
+        if (i < N) {
+          a.Yout[(int64_t)i * C + cell] = D[0];
+        } else {
+          a.Tout[cell] = D[0];
+          a.Eout[cell] = (D[0] - y0v) / nt.inv_cv;
+        }
       }
     }
   } else {
@@ -491,139 +565,148 @@ adjoint_kernel(AdjArgs a) {
     double lam[DROWS];
 #pragma unroll
     for (int j = 0; j < DROWS; ++j) lam[j] = 0.0;
-    if (own) lam[0] = (lane < N) ? a.gY[(int64_t)lane * C + cell] : a.gE[cell] / nt.inv_cv;
-    double gr[GR];
-#pragma unroll
-    for (int u = 0; u < GR; ++u) gr[u] = 0.0;
+    if (own && !dead) lam[0] = (i < N) ? a.gY[(int64_t)i * C + cell] : a.gE[cell] / nt.inv_cv;
+    for (int r = i; r < R; r += G) grl[r] = 0.0;
 
-    // per reaction: w_r = sum_i W_ir mu_i with mu in vbuf; adds
-    // scale * R_r * w_r to the gradient and, if want_jt, scale * w_r * dR_r/dy
-    // into jout (J^T mu).  The state is in ybuf.
-    auto accumulate = [&](double scale, bool want_jt) {
-      if (want_jt && own) jout[lane] = 0.0;
+    // per reaction: w_r = sum_i W_ir mu_i with mu in vbuf; for cells with
+    // act adds scale * R_r * w_r to the gradient and, with want_jt too,
+    // scale * w_r * dR_r/dy into jout (J^T mu).  The state is in ybuf.
+    auto accumulate = [&](double scale, bool want_jt, bool act) {
+      if (want_jt && own) jout[i] = 0.0;
       wave_lds_sync();
       const TPow tp = tpow(ybuf[N]);
-      for (int u = 0; u < GR; ++u) {
-        const int r = lane + 64 * u;
-        if (r >= R) break;
-        double g[4];
-        const double v = rate_and_slots(tb, r, tp, ybuf, rho, want_jt, g);
-        const int4 *ro = reinterpret_cast<const int4 *>(tb.rout + 8 * r);
-        const int4 r0 = ro[0], r1 = ro[1];
-        const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-        double w = tb.qcv[r] * vbuf[N];
-        for (int e = 0; e < r0.x; ++e) w += (double)(signed char)(ent[e] & 0xff) * vbuf[ent[e] >> 8];
-        gr[u] += scale * v * w;
-        if (want_jt) {
-          const int *sp = tb.rsp + 4 * r;
-          for (int s = 0; s < 4; ++s) {
-            const int col = (s < 3) ? sp[s] : N;
-            if (col >= 0) lds_add(&jout[col], w * g[s]);
+      for (int r = i; r < R; r += G) {
+        {
+          double g[4];
+          const double v = rate_and_slots(tb, r, tp, ybuf, rho, want_jt, g);
+          const int4 *ro = reinterpret_cast<const int4 *>(tb.rout + 8 * r);
+          const int4 r0 = ro[0], r1 = ro[1];
+          const int ent[7] = {r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+          double w = tb.qcv[r] * vbuf[N];
+          for (int e = 0; e < r0.x; ++e)
+            w += (double)(signed char)(ent[e] & 0xff) * vbuf[ent[e] >> 8];
+          if (act) grl[r] += scale * v * w;
+          if (want_jt) {
+            const int *sp = tb.rsp + 4 * r;
+            for (int s = 0; s < 4; ++s) {
+              const int col = (s < 3) ? sp[s] : N;
+              if (col >= 0) lds_add(&jout[col], w * g[s]);
+            }
           }
         }
       }
       wave_lds_sync();
     };
 
-    const int n_seg = (n_steps + CK - 1) / CK;
-    for (int sg = n_seg - 1; sg >= 0; --sg) {
+    double *segg = a.seg + (size_t)cell * CK * n;  // corrected states of the segment
+    const int n_seg = (nst + CK - 1) / CK;
+    const int sg_end = wave_max_of_groups<G>(n_seg);
+    for (int sg = sg_end - 1; sg >= 0; --sg) {
       const int m0 = sg * CK;
-      const int m1 = (m0 + CK < n_steps) ? m0 + CK : n_steps;
+      const int m1 = sg < n_seg ? (m0 + CK < nst ? m0 + CK : nst) : m0;
       // recompute the segment from its checkpoint, keeping y_new
-      if (own) {
+      if (m1 > m0 && own) {
         const double *cp = ck + (size_t)sg * 7 * n;
 #pragma unroll
-        for (int j = 0; j < DROWS; ++j) D[j] = cp[j * n + lane];
+        for (int j = 0; j < DROWS; ++j) D[j] = cp[j * n + i];
       }
-      for (int m = m0; m < m1; ++m) {
+      for (int mm = 0; mm < CK; ++mm) {
+        const bool act = m0 + mm < m1;
+        if (__ballot(act) == 0) break;  // later steps of the segment: no cell has them
         double y_new;
-        replay_step(m, y_new);
-        if (own) seg[(m - m0) * n + lane] = y_new;
+        replay_step(m0 + mm, act, y_new);
+        if (act && own) segg[mm * n + i] = y_new;
       }
       // walk it backwards
-      for (int m = m1 - 1; m >= m0; --m) {
-        const int k = so[m];
-        const double ratio = sr[m];
+      for (int mm = CK - 1; mm >= 0; --mm) {
+        const int m = m0 + mm;
+        const bool act = m < m1;
+        if (__ballot(act) == 0) continue;
+        const double ys = (act && own) ? segg[mm * n + i] : 1.0;
+        const int k = act ? so[m] : 1;
+        const double ratio = act ? sr[m] : 1.0;
         double gk = 1.0;
 #pragma unroll
         for (int kk = 1; kk <= KMAX; ++kk)
           if (kk == k) gk = gamma_of(kk);
-        const double c = sh[m] / gk;
+        const double c = act ? sh[m] / gk : 0.0;
         // transpose of the history update D'_{k+1} = d, D'_j = sum_{i=j..k} D_i + d
-        double pre[DROWS];
-        double run = 0.0;
-#pragma unroll
-        for (int j = 0; j < DROWS; ++j) {
-          run += lam[j];
-          pre[j] = run;  // sum_{i<=j} lam_i
-        }
         double ld = 0.0;
+        if (act) {
+          double pre[DROWS];
+          double run = 0.0;
 #pragma unroll
-        for (int kk = 1; kk <= KMAX; ++kk)
-          if (kk == k) {
-            ld = pre[kk] + lam[kk + 1];
-#pragma unroll
-            for (int j = 0; j <= kk; ++j) lam[j] = pre[j];
-            lam[kk + 1] = 0.0;
+          for (int j = 0; j < DROWS; ++j) {
+            run += lam[j];
+            pre[j] = run;  // sum_{i<=j} lam_i
           }
-        // corrector: mu = M^-T lambda_d at y_new
-        if (own) ybuf[lane] = seg[(m - m0) * n + lane];
-        double dummy;
-        eval_f_m(c, false, true, dummy);
-        factor();
-        const double mu = solve_t(ld);
-        if (own) vbuf[lane] = mu;
-        accumulate(c, true);
-        const double ly0 = own ? c * jout[lane] : 0.0;
-        const double lpsi = -mu;
 #pragma unroll
-        for (int j = 0; j <= KMAX; ++j)
-          if (j <= k) lam[j] += ly0;
+          for (int kk = 1; kk <= KMAX; ++kk)
+            if (kk == k) {
+              ld = pre[kk] + lam[kk + 1];
 #pragma unroll
-        for (int j = 1; j <= KMAX; ++j)
-          if (j <= k) lam[j] += (gamma_of(j) / gk) * lpsi;
-        // transpose of the rescale: lam <- (R(rho) U) lam on rows 0..k
-        if (ratio != 1.0) {
-          double w[KMAX + 1];
-#pragma unroll
-          for (int mm = 0; mm <= KMAX; ++mm) {
-            double acc = 0.0;
-#pragma unroll
-            for (int aa = mm; aa <= KMAX; ++aa)
-              if (aa <= k) acc += u_of(mm, aa) * lam[aa];
-            w[mm] = acc;
-          }
-          double nl[KMAX + 1];
-#pragma unroll
-          for (int b = 0; b <= KMAX; ++b) nl[b] = 0.0;
-#pragma unroll
-          for (int mm = 0; mm <= KMAX; ++mm) {
-            if (mm > k) continue;
-            const double x = (double)mm * ratio;
-            double rb = 1.0;
-            nl[0] += w[mm];
-#pragma unroll
-            for (int b = 1; b <= KMAX; ++b) {
-              rb *= ((double)(b - 1) - x) * (1.0 / (double)b);
-              if (b <= k) nl[b] += rb * w[mm];
+              for (int j = 0; j <= kk; ++j) lam[j] = pre[j];
+              lam[kk + 1] = 0.0;
             }
-          }
+        }
+        // corrector: mu = M^-T lambda_d at y_new
+        if (act && own) ybuf[i] = ys;
+        double dummy;
+        eval_f_m(c, false, act, dummy);
+        factor(act);
+        const double mu = solve_t(ld);
+        if (own) vbuf[i] = act ? mu : 0.0;
+        accumulate(c, act, act);
+        if (act) {
+          const double ly0 = own ? c * jout[i] : 0.0;
+          const double lpsi = -mu;
 #pragma unroll
-          for (int b = 0; b <= KMAX; ++b)
-            if (b <= k) lam[b] = nl[b];
+          for (int j = 0; j <= KMAX; ++j)
+            if (j <= k) lam[j] += ly0;
+#pragma unroll
+          for (int j = 1; j <= KMAX; ++j)
+            if (j <= k) lam[j] += (gamma_of(j) / gk) * lpsi;
+          // transpose of the rescale: lam <- (R(rho) U) lam on rows 0..k
+          if (ratio != 1.0) {
+            double w[KMAX + 1];
+#pragma unroll
+            for (int mq = 0; mq <= KMAX; ++mq) {
+              double acc = 0.0;
+#pragma unroll
+              for (int aa = mq; aa <= KMAX; ++aa)
+                if (aa <= k) acc += u_of(mq, aa) * lam[aa];
+              w[mq] = acc;
+            }
+            double nl[KMAX + 1];
+#pragma unroll
+            for (int b = 0; b <= KMAX; ++b) nl[b] = 0.0;
+#pragma unroll
+            for (int mq = 0; mq <= KMAX; ++mq) {
+              if (mq > k) continue;
+              const double x = (double)mq * ratio;
+              double rb = 1.0;
+              nl[0] += w[mq];
+#pragma unroll
+              for (int b = 1; b <= KMAX; ++b) {
+                rb *= ((double)(b - 1) - x) * (1.0 / (double)b);
+                if (b <= k) nl[b] += rb * w[mq];
+              }
+            }
+#pragma unroll
+            for (int b = 0; b <= KMAX; ++b)
+              if (b <= k) lam[b] = nl[b];
+          }
         }
       }
     }
     // D_1 = h_init f(y(0)): its multiplier dependence
     if (own) {
-      ybuf[lane] = y0v;
-      vbuf[lane] = lam[1];
+      ybuf[i] = y0v;
+      vbuf[i] = lam[1];
     }
-    accumulate(blk[1], false);
-    for (int u = 0; u < GR; ++u) {
-      const int r = lane + 64 * u;
-      if (r < R) a.grad[(int64_t)r * C + cell] = gr[u];
-    }
+    accumulate(dead ? 0.0 : blk[1], false, !dead);
+    if (!dead)
+      for (int r = i; r < R; r += G) a.grad[(int64_t)r * C + cell] = grl[r];
   }
 }
 
@@ -631,9 +714,11 @@ adjoint_kernel(AdjArgs a) {
 
 size_t adjoint_sched_stride(int cap) { return 2 + 2 * (size_t)cap + ((size_t)cap + 1) / 2; }
 int adjoint_n_ckpt(int cap) { return (cap + CK - 1) / CK; }
+size_t adjoint_seg_doubles(int n) { return (size_t)CK * n; }
 size_t adjoint_lds_bytes(int R, int n, int waves) {
-  return 8 * (tab_doubles_of(R) + (size_t)waves * adj_wave_doubles(n));
+  return 8 * (tab_doubles_of(R) + (size_t)waves * adj_wave_doubles(n, R));
 }
+int adjoint_cells_per_wave(int n) { return 64 / adj_group(n); }
 
 hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
 #define BN_REC(l, s, w)                                                                          \
@@ -659,20 +744,30 @@ hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipSt
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
                           hipStream_t stream) {
   const size_t lds = adjoint_lds_bytes(a.net.R, a.net.n, waves);
-  const int64_t blocks = (a.n_cells + waves - 1) / waves;
+  const int G = adj_group(a.net.n);
+  const int64_t per_block = (int64_t)waves * (64 / G);
+  const int64_t blocks = (a.n_cells + per_block - 1) / per_block;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(64 * waves);
-  if (backward) {
-    if (simd_waves >= 3)
-      hipLaunchKernelGGL((adjoint_kernel<true, 3>), grid, block, lds, stream, a);
-    else
-      hipLaunchKernelGGL((adjoint_kernel<true, 2>), grid, block, lds, stream, a);
+#define BN_ADJ(bwd, w, g) hipLaunchKernelGGL((adjoint_kernel<bwd, w, g>), grid, block, lds, stream, a)
+  if (G == 32) {
+    if (backward) {
+      if (simd_waves >= 3) BN_ADJ(true, 3, 32);
+      else BN_ADJ(true, 2, 32);
+    } else {
+      if (simd_waves >= 3) BN_ADJ(false, 3, 32);
+      else BN_ADJ(false, 2, 32);
+    }
   } else {
-    if (simd_waves >= 3)
-      hipLaunchKernelGGL((adjoint_kernel<false, 3>), grid, block, lds, stream, a);
-    else
-      hipLaunchKernelGGL((adjoint_kernel<false, 2>), grid, block, lds, stream, a);
+    if (backward) {
+      if (simd_waves >= 3) BN_ADJ(true, 3, 64);
+      else BN_ADJ(true, 2, 64);
+    } else {
+      if (simd_waves >= 3) BN_ADJ(false, 3, 64);
+      else BN_ADJ(false, 2, 64);
+    }
   }
+#undef BN_ADJ
   return hipGetLastError();
 }
 

@@ -827,16 +827,18 @@ namespace {
 struct AdjLayout {
   size_t stride;      // schedule doubles per cell
   int n_ckpt;
-  size_t sched_bytes, ckpt_bytes, total;
+  size_t sched_bytes, ckpt_bytes, seg_bytes, total;
 };
 
+// schedules, then checkpoints, then the reverse sweep's segment states
 AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
   AdjLayout l{};
   l.stride = bn::adjoint_sched_stride(cap);
   l.n_ckpt = bn::adjoint_n_ckpt(cap);
   l.sched_bytes = 8 * l.stride * (size_t)n_cells;
   l.ckpt_bytes = 8 * (size_t)n_cells * l.n_ckpt * 7 * (size_t)net->n;
-  l.total = l.sched_bytes + l.ckpt_bytes;
+  l.seg_bytes = 8 * (size_t)n_cells * bn::adjoint_seg_doubles(net->n);
+  l.total = l.sched_bytes + l.ckpt_bytes + l.seg_bytes;
   return l;
 }
 
@@ -884,6 +886,8 @@ bn::AdjArgs adj_args(const bn_network *net, int64_t n_cells, const double *state
   a.sched_cap = max_steps;
   a.ckpt = reinterpret_cast<double *>(static_cast<char *>(workspace) + l.sched_bytes);
   a.n_ckpt = l.n_ckpt;
+  a.seg = reinterpret_cast<double *>(static_cast<char *>(workspace) + l.sched_bytes +
+                                     l.ckpt_bytes);
   a.rtol = rtol;
   a.atol = atol;
   return a;

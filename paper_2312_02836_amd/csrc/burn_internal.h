@@ -133,7 +133,8 @@ hipError_t launch_stage_out(const BurnArgs &a, const BurnArgs &st, const int32_t
                             hipStream_t stream);
 
 // Sensitivity runs (discrete adjoint with respect to the log-rate
-// multipliers).  The replay / adjoint kernels take one cell per wave.
+// multipliers).  The replay / adjoint kernels take one cell per 32 lanes for
+// systems of up to 32 components, else one per wave.
 struct AdjArgs {
   NetTables net;
   int64_t n_cells;
@@ -149,11 +150,15 @@ struct AdjArgs {
   int sched_cap;
   double *ckpt;                 // [n_cells][n_ckpt][7][n]
   int n_ckpt;
+  double *seg;                  // [n_cells][adjoint_seg_doubles(n)]: corrected states of
+                                // the segment being reversed (backward)
   double rtol, atol;
 };
 size_t adjoint_sched_stride(int cap);  // doubles per cell
 int adjoint_n_ckpt(int cap);
+size_t adjoint_seg_doubles(int n);    // per cell
 size_t adjoint_lds_bytes(int R, int n, int waves);
+int adjoint_cells_per_wave(int n);
 hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
 // simd_waves: 3 or 2, the register budget of the kernel instance to launch
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
