@@ -291,8 +291,11 @@ int bn_network_get_launch(const bn_network *net, int32_t *lanes_per_cell,
  * Workspace: caller-provided DEVICE memory of
  * burn_batch_adjoint_workspace_bytes(net, n_cells, max_steps) bytes, 8-byte
  * aligned, holding per cell the schedule (20 bytes per step of max_steps),
- * a checkpoint of 7 (N + 1) doubles every 16 steps, and the corrected states
- * of one 16-step segment for the reverse sweep; the forward call fills it,
+ * a checkpoint of 7 (N + 1) doubles every 16 steps, the corrected states of
+ * one 16-step segment for the reverse sweep, and the order in which the
+ * replay and the reverse sweep take the cells (most recorded steps first,
+ * so that the cells sharing a wave have similar step counts; 12 bytes per
+ * cell); the forward call fills it,
  * the backward call reads it (same net, cells, dt, tolerances, log_mult and
  * max_steps), and it must not be shared by calls in flight.
  * max_steps (1 .. 1,000,000) bounds the accepted steps of a cell; a cell that

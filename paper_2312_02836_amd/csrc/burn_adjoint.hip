@@ -193,7 +193,9 @@ adjoint_kernel(AdjArgs a) {
   const int64_t first = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * CPW;
   if (first >= C) return;  // whole wave: no later workgroup barrier
   const bool valid = first + cs < C;
-  const int64_t cell = valid ? first + cs : C - 1;  // an empty slot reads a real cell
+  // the cell at this position (an empty slot reads a real cell)
+  const int64_t p = valid ? first + cs : C - 1;
+  const int64_t cell = a.order ? (int64_t)a.order[p] : p;
 
   double *wb = smem + tab_doubles_of(R) + (size_t)wave * adj_wave_doubles(n, R) +
                (size_t)cs * adj_cell_doubles(n, R);
@@ -710,6 +712,23 @@ adjoint_kernel(AdjArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) adj_key_kernel(AdjArgs a, float *key) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_cells) return;
+  // fewer accepted steps -> larger key -> later position; 16 steps per
+  // octave, i.e. buckets of 8 steps up to ~1,000 steps (longer runs share
+  // the first bucket); failed runs (no steps recorded) last
+  const double ns = a.sched[c * a.sched_stride];
+  key[c] = (ns >= 0.0 && a.status[c] == ST_OK) ? exp2f(-(float)ns * (1.0f / 16.0f))
+                                                : __builtin_inff();
+}
+
+__global__ void __launch_bounds__(256) adj_inverse_kernel(const int32_t *pos, int64_t n,
+                                                          int32_t *order) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) order[pos[c]] = (int32_t)c;
+}
+
 }  // namespace
 
 size_t adjoint_sched_stride(int cap) { return 2 + 2 * (size_t)cap + ((size_t)cap + 1) / 2; }
@@ -739,6 +758,21 @@ hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipSt
   BN_REC(64, 1, 1)
 #undef BN_REC
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint_order(const AdjArgs &a, float *key, int32_t *pos, unsigned *hist,
+                                int32_t *order, hipStream_t stream) {
+  const int64_t n = a.n_cells;
+  if (n <= 0) return hipSuccess;
+  if (n > 0x7fffffff) return hipErrorInvalidValue;
+  hipError_t e = launch_zero(reinterpret_cast<unsigned long long *>(hist), ORDER_BUCKETS, stream);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(adj_key_kernel, dim3(blocks), dim3(256), 0, stream, a, key);
+  e = launch_sort_keys(key, n, pos, hist, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(adj_inverse_kernel, dim3(blocks), dim3(256), 0, stream, pos, n, order);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,

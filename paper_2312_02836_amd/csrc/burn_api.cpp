@@ -827,10 +827,13 @@ namespace {
 struct AdjLayout {
   size_t stride;      // schedule doubles per cell
   int n_ckpt;
-  size_t sched_bytes, ckpt_bytes, seg_bytes, total;
+  size_t sched_bytes, ckpt_bytes, seg_bytes;
+  size_t o_key, o_pos, o_order, o_hist;  // the cell order (costliest first)
+  size_t total;
 };
 
-// schedules, then checkpoints, then the reverse sweep's segment states
+// schedules, checkpoints, the reverse sweep's segment states, then the cell
+// order's sort keys, positions, order and bucket counters (256-byte aligned)
 AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
   AdjLayout l{};
   l.stride = bn::adjoint_sched_stride(cap);
@@ -838,7 +841,16 @@ AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
   l.sched_bytes = 8 * l.stride * (size_t)n_cells;
   l.ckpt_bytes = 8 * (size_t)n_cells * l.n_ckpt * 7 * (size_t)net->n;
   l.seg_bytes = 8 * (size_t)n_cells * bn::adjoint_seg_doubles(net->n);
-  l.total = l.sched_bytes + l.ckpt_bytes + l.seg_bytes;
+  size_t o = align256(l.sched_bytes + l.ckpt_bytes + l.seg_bytes);
+  l.o_key = o;
+  o += align256(4 * (size_t)n_cells);
+  l.o_pos = o;
+  o += align256(4 * (size_t)n_cells);
+  l.o_order = o;
+  o += align256(4 * (size_t)n_cells);
+  l.o_hist = o;
+  o += align256(8 * (size_t)bn::ORDER_BUCKETS);
+  l.total = o;
   return l;
 }
 
@@ -888,6 +900,7 @@ bn::AdjArgs adj_args(const bn_network *net, int64_t n_cells, const double *state
   a.n_ckpt = l.n_ckpt;
   a.seg = reinterpret_cast<double *>(static_cast<char *>(workspace) + l.sched_bytes +
                                      l.ckpt_bytes);
+  a.order = reinterpret_cast<const int32_t *>(static_cast<char *>(workspace) + l.o_order);
   a.rtol = rtol;
   a.atol = atol;
   return a;
@@ -972,6 +985,17 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
     return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
   hipError_t e = bn::launch_record(b, L, S, bw, st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("recording launch failed: ") + hipGetErrorString(e));
+  {
+    // replay and reverse sweep take the cells most recorded steps first
+    const AdjLayout l = adj_layout(net, n_cells, max_steps);
+    char *w = static_cast<char *>(workspace);
+    e = bn::launch_adjoint_order(a, reinterpret_cast<float *>(w + l.o_key),
+                                 reinterpret_cast<int32_t *>(w + l.o_pos),
+                                 reinterpret_cast<unsigned *>(w + l.o_hist),
+                                 reinterpret_cast<int32_t *>(w + l.o_order), st);
+    if (e != hipSuccess)
+      return fail(BN_EHIP, std::string("cell order launch failed: ") + hipGetErrorString(e));
+  }
   a.Yout = state_out;
   a.Tout = T_out;
   a.Eout = E_out;

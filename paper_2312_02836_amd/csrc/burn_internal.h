@@ -124,6 +124,10 @@ hipError_t noalloc_scratch(void **out);
 constexpr int ORDER_BUCKETS = 128;
 hipError_t launch_order(const BurnArgs &a, float *key, int32_t *pos, unsigned *hist,
                         size_t lds_block, hipStream_t stream);
+// The counting sort alone: pos[c] for n keys (smallest first, 128 buckets of
+// two per octave, positions dealt into XCD_PARTS parts as for the queue).
+hipError_t launch_sort_keys(const float *key, int64_t n, int32_t *pos, unsigned *hist,
+                            hipStream_t stream);
 // staged copy of an item: st.Y, st.T, st.rho, st.status, st.counters point
 // to position-ordered arrays of the item's size (status/counters null when
 // the item's are)
@@ -152,6 +156,8 @@ struct AdjArgs {
   int n_ckpt;
   double *seg;                  // [n_cells][adjoint_seg_doubles(n)]: corrected states of
                                 // the segment being reversed (backward)
+  const int32_t *order;         // [n_cells] cell at each position (costliest first), or
+                                // nullptr for index order
   double rtol, atol;
 };
 size_t adjoint_sched_stride(int cap);  // doubles per cell
@@ -160,6 +166,11 @@ size_t adjoint_seg_doubles(int n);    // per cell
 size_t adjoint_lds_bytes(int R, int n, int waves);
 int adjoint_cells_per_wave(int n);
 hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
+// Order of the cells for the replay and reverse sweep, from the recorded
+// step counts (most steps first): key, pos and hist are scratch (hist zeroed
+// by the call), order receives the cell at each position.
+hipError_t launch_adjoint_order(const AdjArgs &a, float *key, int32_t *pos, unsigned *hist,
+                                int32_t *order, hipStream_t stream);
 // simd_waves: 3 or 2, the register budget of the kernel instance to launch
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
                           hipStream_t stream);

@@ -330,6 +330,13 @@ hipError_t launch_order(const BurnArgs &item, float *key, int32_t *pos, unsigned
                  : sz <= 32 ? launch_probe_t<32, 1>(a, lds_block, stream)
                             : launch_probe_t<64, 1>(a, lds_block, stream);
   if (e != hipSuccess) return e;
+  return launch_sort_keys(key, n, pos, hist, stream);
+}
+
+hipError_t launch_sort_keys(const float *key, int64_t n, int32_t *pos, unsigned *hist,
+                            hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (n > 0x7fffffff) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, stream, key, n, hist);
   hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, stream, hist);
