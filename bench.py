@@ -153,6 +153,21 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
         b["cnt"] = torch.empty((8, n_cells), dtype=torch.int32, device=dev)
         batches.append(b)
     opts = _lib.BurnOpts(0, 0, args.block_waves, 0)
+    # the persistent kernel's launch choice per network: from the tuning
+    # cache, or tuned on the first 16,384 cells (outside the timed region)
+    tune = []
+    if not args.no_tune and not (args.lanes or args.block_waves):
+        for b in batches:
+            k = min(16384, n_cells)
+            t0 = time.perf_counter()
+            e = B.tune_cached(b["net"], b["Y0"][:, :k].contiguous(), b["rho"][:k].contiguous(),
+                              b["T0"][:k].contiguous(), cfg.t_end, cfg.rtol, cfg.atol)
+            tune.append({"network": f"{b['spec'].n_species}/{b['spec'].n_reactions}",
+                         "choice": e["persistent"], "cache_hit": e["hit"],
+                         "sample_cells": e["sample_cells"],
+                         "seconds": round(time.perf_counter() - t0, 2)})
+            log(f"{wl_name}: persistent choice {e['persistent']} "
+                f"({'cache' if e['hit'] else 'tuned'})")
 
     def restore():
         for b in batches:
@@ -252,6 +267,8 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
               "networks": [f"{b['spec'].n_species}/{b['spec'].n_reactions}" for b in batches],
               "t_end": cfg.t_end, "kernel": kernel_name, "graph_replay": use_graph,
               "launch": [list(b["net"].get_launch()) for b in batches],
+              "persistent_launch": [list(b["net"].get_persistent_launch()) for b in batches],
+              "persistent_tuning": tune,
               "steps_mean_p5_p95": step_stats}
     config[f"{'plain' if wl['mode'] == 'plain' else 'persistent'}_kernel_ms"] = kernel_ms
     if other is not None:
@@ -441,6 +458,8 @@ def main() -> int:
     ap.add_argument("--no-compare", action="store_true",
                     help="time only the workload's schedule (not the other one beside it)")
     ap.add_argument("--no-sub", action="store_true", help="headline workload only")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="persistent launches with the derived (untuned) choice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-seconds-1thread", type=float, default=8.0)

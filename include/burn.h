@@ -185,7 +185,9 @@ size_t burn_batch_multi_workspace_bytes(int32_t n_items);
 size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_item *items);
 
 /* Burn the cells of up to BN_MAX_ITEMS networks (same dt and tolerances) in
- * ONE persistent kernel launch with a device work queue: the grid is sized to
+ * ONE persistent kernel launch with a device work queue (one per
+ * waves-per-SIMD class of the networks' persistent choices, see
+ * bn_network_set_persistent_launch): the grid is sized to
  * the GPU, and each lane group that finishes a cell takes the next unstarted
  * cell of the current network, so cells of uneven stiffness and networks of
  * different sizes share the machine without per-batch tails.  Per-cell
@@ -272,6 +274,49 @@ int bn_network_set_launch(bn_network *net, int32_t lanes_per_cell, int32_t slots
                           int32_t block_waves);
 int bn_network_get_launch(const bn_network *net, int32_t *lanes_per_cell,
                           int32_t *slots_per_lane, int32_t *block_waves);
+
+/* The persistent kernel's launch choice for a network: lanes per cell,
+ * slots per lane, the waves per SIMD its instance is compiled for (2: shapes
+ * (8,1) (16,1) (32,1) (64,1); 1: (4,4) (16,2) (32,1) (64,1)) and the waves per
+ * workgroup.  burn_batch_multi runs each network with its choice and gives
+ * the networks of each waves-per-SIMD class a launch of their own (one
+ * launch per class, in a call that has both). */
+typedef struct {
+  int32_t lanes_per_cell;
+  int32_t slots_per_lane;
+  int32_t waves_per_simd; /* 2 or 1 */
+  int32_t block_waves;    /* waves per workgroup, 1..4 */
+  int32_t status;         /* 0 measured, else the error of that candidate (skipped) */
+  double ms;              /* time of an ordered persistent launch of the sample */
+} bn_persistent_tune_result;
+
+/* Time every persistent launch choice that fits this network (shapes with
+ * L*S >= n and not mostly padding, both waves-per-SIMD classes, 1, 2 and 4
+ * waves per workgroup) on a sample of cells, each as an ordered
+ * burn_batch_multi launch of the sample alone, and make the fastest the
+ * network's persistent choice (and its time per cell the network's cost
+ * estimate).  The caller's arrays are only read.  Synchronizes `stream`;
+ * allocates device memory; not for use under graph capture.
+ *   state, rho, T  DEVICE sample in the burn_batch layout (n_cells >= 1)
+ *   results        HOST [max_results] or NULL; *n_results = entries written
+ * Returns BN_SUCCESS or a negative code (the previous choice is kept). */
+int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const double *state,
+                                   const double *rho, const double *T, double dt, double rtol,
+                                   double atol, const double *log_mult, int32_t max_steps,
+                                   bn_persistent_tune_result *results, int32_t max_results,
+                                   int32_t *n_results, void *stream);
+
+/* Set the persistent choice directly (e.g. from a cached tuning);
+ * lanes_per_cell = 0 clears it.  ms_per_cell > 0 also sets the network's
+ * cost estimate (the order in which a multi-network launch takes its
+ * networks).  Get reports the choice a launch would use now (the tuned one,
+ * or the one derived from the plain choice and the LDS footprint). */
+int bn_network_set_persistent_launch(bn_network *net, int32_t lanes_per_cell,
+                                     int32_t slots_per_lane, int32_t waves_per_simd,
+                                     int32_t block_waves, double ms_per_cell);
+int bn_network_get_persistent_launch(const bn_network *net, int32_t *lanes_per_cell,
+                                     int32_t *slots_per_lane, int32_t *waves_per_simd,
+                                     int32_t *block_waves);
 
 /* ---- Sensitivities: discrete adjoint in the log-rate multipliers ------- */
 

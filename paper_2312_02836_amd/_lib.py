@@ -23,7 +23,8 @@ EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "bn_network_n_reactions", "burn_batch", "burn_batch_ex",
            "burn_batch_multi_workspace_bytes", "burn_batch_multi_order_workspace_bytes",
            "burn_batch_multi", "burn_batch_multi_noalloc", "bn_network_autotune",
-           "bn_network_set_launch", "bn_network_get_launch",
+           "bn_network_set_launch", "bn_network_get_launch", "bn_network_autotune_persistent",
+           "bn_network_set_persistent_launch", "bn_network_get_persistent_launch",
            "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
            "burn_batch_adjoint_backward", "burn_batch_adjoint", "burn_batch_sdc",
            "bn_last_error", "bn_version"]
@@ -52,6 +53,12 @@ class BatchItem(C.Structure):
 class TuneResult(C.Structure):
     _fields_ = [("lanes_per_cell", C.c_int32), ("slots_per_lane", C.c_int32),
                 ("block_waves", C.c_int32), ("status", C.c_int32), ("ms", C.c_double)]
+
+
+class PersistentTuneResult(C.Structure):
+    _fields_ = [("lanes_per_cell", C.c_int32), ("slots_per_lane", C.c_int32),
+                ("waves_per_simd", C.c_int32), ("block_waves", C.c_int32),
+                ("status", C.c_int32), ("ms", C.c_double)]
 
 
 class BurnError(RuntimeError):
@@ -95,6 +102,18 @@ def lib() -> C.CDLL:
                                       C.c_double, dp, C.c_int32, C.POINTER(TuneResult),
                                       C.c_int32, C.POINTER(C.c_int32), vp]
     L.bn_network_autotune.restype = C.c_int
+    L.bn_network_autotune_persistent.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double,
+                                                 C.c_double, C.c_double, dp, C.c_int32,
+                                                 C.POINTER(PersistentTuneResult), C.c_int32,
+                                                 C.POINTER(C.c_int32), vp]
+    L.bn_network_autotune_persistent.restype = C.c_int
+    L.bn_network_set_persistent_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32,
+                                                   C.c_int32, C.c_double]
+    L.bn_network_set_persistent_launch.restype = C.c_int
+    L.bn_network_get_persistent_launch.argtypes = [vp, C.POINTER(C.c_int32),
+                                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                                   C.POINTER(C.c_int32)]
+    L.bn_network_get_persistent_launch.restype = C.c_int
     L.bn_network_set_launch.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
     L.bn_network_set_launch.restype = C.c_int
     L.bn_network_get_launch.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),

@@ -6,6 +6,9 @@ runs in the HIP kernels of libburn.so.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
+import json
+import os
 import warnings
 from typing import Optional, Tuple
 
@@ -52,6 +55,39 @@ class Network:
         _lib.check(_lib.lib().bn_network_get_launch(self.handle, C.byref(a), C.byref(b),
                                                     C.byref(c)), "bn_network_get_launch")
         return a.value, b.value, c.value
+
+    def set_persistent_launch(self, lanes_per_cell: int, slots_per_lane: int = 1,
+                              waves_per_simd: int = 2, block_waves: int = 4,
+                              ms_per_cell: float = 0.0) -> None:
+        """Fix the persistent kernel's launch choice (0 lanes = derive it per call)."""
+        _lib.check(_lib.lib().bn_network_set_persistent_launch(
+            self.handle, lanes_per_cell, slots_per_lane, waves_per_simd, block_waves,
+            float(ms_per_cell)), "bn_network_set_persistent_launch")
+
+    def get_persistent_launch(self) -> Tuple[int, int, int, int]:
+        """(lanes per cell, slots per lane, waves per SIMD, waves per workgroup)."""
+        v = [C.c_int32() for _ in range(4)]
+        _lib.check(_lib.lib().bn_network_get_persistent_launch(self.handle,
+                                                               *[C.byref(x) for x in v]),
+                   "bn_network_get_persistent_launch")
+        return tuple(x.value for x in v)
+
+    def cache_key(self, device=None) -> str:
+        """Key of this network's tunings: a hash of its tables, its size, the
+        GPU architecture and the library version."""
+        import torch
+        h = hashlib.sha256()
+        for a in (self.spec.mass, self.spec.reactants, self.spec.products, self.spec.coef,
+                  self.spec.q):
+            h.update(np.ascontiguousarray(a).tobytes())
+        h.update(repr(float(self.spec.c_v)).encode())
+        if self.spec.screen is not None:
+            h.update(np.ascontiguousarray(self.spec.screen).tobytes())
+        dev = device if device is not None else torch.cuda.current_device()
+        arch = torch.cuda.get_device_properties(dev).gcnArchName
+        ver = _lib.lib().bn_version().decode()
+        return (f"{h.hexdigest()[:32]}|n={self.spec.n}|R={self.spec.n_reactions}|{arch}|"
+                f"{ver}")
 
     @property
     def n_species(self) -> int:
@@ -249,6 +285,67 @@ def autotune(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float
     _lib.check(rc, "bn_network_autotune")
     return [(r.lanes_per_cell, r.slots_per_lane, r.block_waves, r.ms if r.status == 0 else None)
             for r in res[:nres.value]]
+
+
+def autotune_persistent(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6,
+                        atol: float = 1e-10, log_mult=None, *, max_steps: int = 0,
+                        device: Optional[torch.device] = None):
+    """Time every persistent launch choice on a sample of cells and make the
+    fastest the network's persistent choice.  Returns [(L, S, waves per
+    SIMD, block waves, ms or None), ...]."""
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    Yd, rhod, Td = _dev_f64(Y, device), _dev_f64(rho, device), _dev_f64(T, device)
+    lm = None if log_mult is None else _dev_f64(log_mult, device)
+    res = (_lib.PersistentTuneResult * 64)()
+    nres = C.c_int32()
+    stream = torch.cuda.current_stream(device).cuda_stream
+    rc = _lib.lib().bn_network_autotune_persistent(
+        net.handle, rhod.shape[0], _ptr(Yd), _ptr(rhod), _ptr(Td), float(dt), float(rtol),
+        float(atol), _ptr(lm), int(max_steps), res, 64, C.byref(nres), C.c_void_p(stream))
+    _lib.check(rc, "bn_network_autotune_persistent")
+    return [(r.lanes_per_cell, r.slots_per_lane, r.waves_per_simd, r.block_waves,
+             r.ms if r.status == 0 else None) for r in res[:nres.value]]
+
+
+def default_tune_cache() -> str:
+    """$BURN_TUNE_CACHE, else ~/.cache/paper_2312_02836_amd/tune.json."""
+    return os.environ.get("BURN_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "paper_2312_02836_amd", "tune.json")
+
+
+def tune_cached(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6, atol: float = 1e-10,
+                *, cache: Optional[str] = None, device: Optional[torch.device] = None) -> dict:
+    """The network's persistent launch choice from the tuning cache (a JSON
+    file keyed by Network.cache_key: network hash, n, R, GPU architecture,
+    library version), or, on a miss, from autotune_persistent on the given
+    sample, then stored.  Applies the choice to the network and returns the
+    cache entry (with "hit": True when it came from the file)."""
+    path = cache or default_tune_cache()
+    key = net.cache_key(device)
+    entries = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            entries = json.load(f)
+    e = entries.get(key)
+    if e is not None:
+        L_, S_, W_, bw = e["persistent"]
+        net.set_persistent_launch(L_, S_, W_, bw, e.get("ms_per_cell", 0.0))
+        return dict(e, hit=True)
+    results = autotune_persistent(net, Y, rho, T, dt, rtol, atol, device=device)
+    choice = list(net.get_persistent_launch())
+    timed = [r for r in results if r[4] is not None]
+    best_ms = min(r[4] for r in timed)
+    n_sample = int(rho.shape[0])
+    e = {"persistent": choice, "ms_per_cell": best_ms / n_sample,
+         "sample_cells": n_sample, "dt": float(dt),
+         "candidates": [list(r) for r in results]}
+    entries[key] = e
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(entries, f, indent=1)
+    os.replace(tmp, path)
+    return dict(e, hit=False)
 
 
 class AdjointRun:

@@ -21,9 +21,12 @@ struct bn_network {
   int device = 0;
   void *dev = nullptr;  // one allocation holding every table
   bn::NetTables tables{};
-  // launch choice (0 = default for the system size)
+  // plain launch choice (0 = default for the system size)
   int L = 0, S = 0, block_waves = 0;
   double ms_per_cell = 0.0;  // measured by the autotuner (0 = unknown)
+  // persistent launch choice (pW = 0: chosen per call from the plain choice
+  // and the LDS footprint)
+  int pL = 0, pS = 0, pW = 0, pbw = 0;
   bool screened = false;
 };
 
@@ -462,8 +465,59 @@ size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_it
 
 namespace {
 
+// How an item runs in a persistent launch.
+struct ItemLaunch {
+  int W;      // waves per SIMD the kernel instance is compiled for (2 or 1)
+  int L, S;   // shape
+  int shape;  // index into MULTI_SHAPES_2 (W = 2) or MULTI_SHAPES_1 (W = 1)
+  int bw;     // waves per workgroup
+};
+
+// The network's tuned persistent choice if it has one (bn_network_autotune_
+// persistent); else two waves per SIMD with the network's plain choice when
+// the two-wave kernel has that shape, or the default shape; else (a plain
+// choice only the one-wave kernel has, or an LDS footprint that leaves fewer
+// than six waves resident per CU at two) one wave per SIMD.  bw_opt
+// overrides the waves per workgroup.
+ItemLaunch item_launch(const bn_network *net, const DeviceLimits &lim, int bw_opt) {
+  ItemLaunch r{};
+  const int n = net->n;
+  if (net->pW) {
+    r.W = net->pW;
+    r.L = net->pL;
+    r.S = net->pS;
+    r.bw = bw_opt ? bw_opt : net->pbw;
+  } else {
+    r.W = 2;
+    r.L = net->L;
+    r.S = net->S;
+    if (r.L && multi_shape_index(r.L, r.S) < 0 && multi1_shape_index(r.L, r.S) >= 0) r.W = 1;
+    if (r.W == 2 && (!r.L || multi_shape_index(r.L, r.S) < 0)) default_multi_shape(n, &r.L, &r.S);
+    r.bw = bw_opt ? bw_opt : 4;
+    if (r.W == 2) {
+      const size_t tab = bn::table_lds_bytes(net->R), wave = bn::wave_lds_bytes(r.L, r.S, n);
+      int bw = r.bw;
+      while (bw > 1 && tab + (size_t)bw * wave > lim.lds_block) bw /= 2;
+      const size_t lds = tab + (size_t)bw * wave;
+      const size_t resident = std::min<size_t>(8 / bw, lim.lds_cu / lds) * bw;
+      if (resident < 6) {
+        r.W = 1;
+        r.L = net->L;
+        r.S = net->S;
+      }
+    }
+    if (r.W == 1 && (!r.L || multi1_shape_index(r.L, r.S) < 0))
+      default_multi1_shape(n, &r.L, &r.S);
+  }
+  r.shape = r.W == 2 ? multi_shape_index(r.L, r.S) : multi1_shape_index(r.L, r.S);
+  return r;
+}
+
 // burn_batch_multi with the workspace given (the caller's, or the library's
-// static scratch for burn_batch_multi_noalloc).
+// static scratch for burn_batch_multi_noalloc).  Items that run at the same
+// waves per SIMD share one persistent launch; a call with items of both
+// kinds makes two launches, so that small networks are not held to the
+// occupancy of large ones.
 int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rtol, double atol,
                const bn_burn_opts *opts, void *workspace, size_t workspace_bytes, void *stream) {
   if (n_items < 0 || n_items > BN_MAX_ITEMS)
@@ -485,13 +539,10 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
   // validate and collect the non-empty items
   struct It {
     bn::BurnArgs a;
-    int L, S;  // the network's launch choice (0: none)
-    int shape;
+    ItemLaunch l;
     double cost;
   };
   std::vector<It> its;
-  int64_t total = 0;
-  size_t tabd = 0, waved = 0;
   for (int j = 0; j < n_items; ++j) {
     const bn_batch_item &x = items[j];
     if (!x.net) return fail(BN_EINVAL, "null network in item " + std::to_string(j));
@@ -503,8 +554,9 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     if (!x.state || !x.rho || !x.T)
       return fail(BN_EINVAL, "null state, rho or T in item " + std::to_string(j));
     It it{};
-    it.L = x.net->L;
-    it.S = x.net->S;
+    it.l = item_launch(x.net, lim, o.block_waves);
+    if (it.l.shape < 0) return fail(BN_EUNSUPPORTED, "no persistent kernel shape for item " +
+                                                         std::to_string(j));
     bn::BurnArgs &a = it.a;
     a.net = x.net->tables;
     a.n_cells = x.n_cells;
@@ -520,94 +572,41 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     a.max_steps = o.max_steps;
     // cost per cell: measured if tuned, else a size model (LU ~ n^3, RHS ~ R)
     const double n = x.net->n;
-    it.cost = x.net->ms_per_cell > 0.0 ? x.net->ms_per_cell : 1e-6 * (n * n * n + 40.0 * x.net->R);
+    const double per = x.net->ms_per_cell > 0.0 ? x.net->ms_per_cell
+                                                 : 1e-6 * (n * n * n + 40.0 * x.net->R);
+    it.cost = per * (double)x.n_cells;
     its.push_back(it);
-    total += x.n_cells;
   }
   if (its.empty()) return BN_SUCCESS;
-  // Two waves per SIMD unless a network's launch choice is a one-wave shape,
-  // or LDS would hold fewer than 6 waves per CU at two (the largest networks).
-  auto assign = [&](int W) {
-    tabd = 0;
-    waved = 0;
-    for (It &it : its) {
-      int L = it.L, S = it.S;
-      const int n = it.a.net.n;
-      if (W == 2) {
-        if (!L || multi_shape_index(L, S) < 0) default_multi_shape(n, &L, &S);
-        it.shape = multi_shape_index(L, S);
-      } else {
-        if (!L || multi1_shape_index(L, S) < 0) default_multi1_shape(n, &L, &S);
-        it.shape = multi1_shape_index(L, S);
-      }
-      tabd = std::max(tabd, bn::table_lds_bytes(it.a.net.R) / 8);
-      waved = std::max(waved, bn::wave_lds_bytes(L, S, n) / 8);
-    }
-  };
-  auto block_waves_for = [&](int bw0) {
-    int bw = bw0;
-    while (bw > 1 && 8 * (tabd + (size_t)bw * waved) > lim.lds_block) bw /= 2;
-    return bw;
-  };
-  int W = 2;
-  for (const It &it : its)
-    if (it.L && multi_shape_index(it.L, it.S) < 0 && multi1_shape_index(it.L, it.S) >= 0) W = 1;
-  assign(W);
-  if (W == 2) {
-    const int bw = block_waves_for(o.block_waves ? o.block_waves : 4);
-    const size_t lds = 8 * (tabd + (size_t)bw * waved);
-    const size_t resident = std::min<size_t>(8 / bw, lim.lds_cu / lds) * bw;
-    if (resident < 6) {
-      W = 1;
-      assign(W);
-    }
-  }
   const size_t need = o.order_cells ? burn_batch_multi_order_workspace_bytes(n_items, items)
-                                    : burn_batch_multi_workspace_bytes((int32_t)its.size());
+                                    : burn_batch_multi_workspace_bytes(n_items);
   if (!workspace || workspace_bytes < need)
     return fail(BN_EINVAL, o.order_cells
                                ? "workspace missing or smaller than burn_batch_multi_order_workspace_bytes"
                                : "workspace missing or smaller than burn_batch_multi_workspace_bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 8)
     return fail(BN_EINVAL, "workspace must be 8-byte aligned");
-  // costliest cells first, so the tail of the launch is made of cheap cells
-  std::stable_sort(its.begin(), its.end(), [](const It &x, const It &y) { return x.cost > y.cost; });
-
-  bn::MultiArgs m{};
-  m.n_items = (int)its.size();
-  for (int j = 0; j < m.n_items; ++j) {
-    m.item[j] = its[j].a;
-    m.shape[j] = its[j].shape;
-  }
-  m.queue = static_cast<unsigned long long *>(workspace);
-  m.tab_doubles = tabd;
-  m.wave_doubles = waved;
-  // W waves per SIMD (4 W per CU).  Workgroups of block_waves waves; as many
-  // workgroups per CU as LDS allows, up to 4 W waves per CU.
-  const int bw = block_waves_for(o.block_waves ? o.block_waves : 4);
-  const size_t lds = 8 * (tabd + (size_t)bw * waved);
-  if (lds > lim.lds_block)
-    return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
-  m.block_waves = bw;
-  int per_cu = std::max(1, 4 * W / bw);
-  per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, lim.lds_cu / lds));
-  int64_t grid = (int64_t)lim.cus * per_cu;
-  // no more workgroups than there are cells to start
-  const int64_t cells_per_wg = (int64_t)bw * 16;
-  grid = std::max<int64_t>(1, std::min<int64_t>(grid, (total + cells_per_wg - 1) / cells_per_wg));
+  // two-wave class first, each class costliest network first (its cells then
+  // start first and the tail is made of cheap ones)
+  std::stable_sort(its.begin(), its.end(), [](const It &x, const It &y) {
+    if (x.l.W != y.l.W) return x.l.W > y.l.W;
+    return x.cost > y.cost;
+  });
 
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = bn::launch_zero(m.queue, m.n_items, st);
+  unsigned long long *queue = static_cast<unsigned long long *>(workspace);
+  hipError_t e = bn::launch_zero(queue, (int)its.size(), st);
   if (e != hipSuccess)
     return fail(BN_EHIP, std::string("counter reset launch failed: ") + hipGetErrorString(e));
   // ordered: each item's cells are staged in order of increasing initial
   // step size (stiffest first), burnt in that order and written back
-  bn::BurnArgs orig[BN_MAX_ITEMS];
-  int32_t *posv[BN_MAX_ITEMS] = {};
+  std::vector<bn::BurnArgs> orig(its.size()), staged(its.size());
+  std::vector<int32_t *> posv(its.size(), nullptr);
+  for (size_t j = 0; j < its.size(); ++j) staged[j] = orig[j] = its[j].a;
   if (o.order_cells) {
     char *p = static_cast<char *>(workspace) + burn_batch_multi_workspace_bytes(n_items);
-    for (int j = 0; j < m.n_items; ++j) {
-      const bn::BurnArgs a = m.item[j];
+    for (size_t j = 0; j < its.size(); ++j) {
+      const bn::BurnArgs &a = orig[j];
       const OrderLayout l = order_layout(a.n_cells, a.net.N);
       unsigned *hist = reinterpret_cast<unsigned *>(p + l.hist);
       float *key = reinterpret_cast<float *>(p + l.key);
@@ -626,16 +625,52 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
       if (e == hipSuccess) e = bn::launch_stage_in(a, s, pos, st);
       if (e != hipSuccess)
         return fail(BN_EHIP, std::string("queue order launch failed: ") + hipGetErrorString(e));
-      orig[j] = a;
       posv[j] = pos;
-      m.item[j] = s;
+      staged[j] = s;
     }
   }
-  e = bn::launch_multi(m, (int)grid, W, st);
-  if (e != hipSuccess) return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  // one persistent launch per class
+  for (size_t c0 = 0; c0 < its.size();) {
+    size_t c1 = c0;
+    while (c1 < its.size() && its[c1].l.W == its[c0].l.W) ++c1;
+    const int W = its[c0].l.W;
+    bn::MultiArgs m{};
+    m.n_items = (int)(c1 - c0);
+    size_t tabd = 0, waved = 0;
+    int64_t total = 0;
+    for (size_t j = c0; j < c1; ++j) {
+      m.item[j - c0] = staged[j];
+      m.shape[j - c0] = its[j].l.shape;
+      tabd = std::max(tabd, bn::table_lds_bytes(its[j].a.net.R) / 8);
+      waved = std::max(waved, bn::wave_lds_bytes(its[j].l.L, its[j].l.S, its[j].a.net.n) / 8);
+      total += its[j].a.n_cells;
+    }
+    m.queue = queue + c0;
+    m.tab_doubles = tabd;
+    m.wave_doubles = waved;
+    // workgroups of bw waves (the costliest network's choice, halved while
+    // the LDS of a workgroup does not fit); as many per CU as LDS allows, up
+    // to 4 W waves per CU
+    int bw = its[c0].l.bw;
+    while (bw > 1 && 8 * (tabd + (size_t)bw * waved) > lim.lds_block) bw /= 2;
+    const size_t lds = 8 * (tabd + (size_t)bw * waved);
+    if (lds > lim.lds_block)
+      return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
+    m.block_waves = bw;
+    int per_cu = std::max(1, 4 * W / bw);
+    per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, lim.lds_cu / lds));
+    int64_t grid = (int64_t)lim.cus * per_cu;
+    // no more workgroups than there are cells to start
+    const int64_t cells_per_wg = (int64_t)bw * 16;
+    grid = std::max<int64_t>(1, std::min<int64_t>(grid, (total + cells_per_wg - 1) / cells_per_wg));
+    e = bn::launch_multi(m, (int)grid, W, st);
+    if (e != hipSuccess)
+      return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    c0 = c1;
+  }
   if (o.order_cells) {
-    for (int j = 0; j < m.n_items; ++j) {
-      e = bn::launch_stage_out(orig[j], m.item[j], posv[j], st);
+    for (size_t j = 0; j < its.size(); ++j) {
+      e = bn::launch_stage_out(orig[j], staged[j], posv[j], st);
       if (e != hipSuccess)
         return fail(BN_EHIP, std::string("write-back launch failed: ") + hipGetErrorString(e));
     }
@@ -677,6 +712,49 @@ int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double
                              hipGetErrorString(e));
   return multi_impl(n_items, items, dt, rtol, atol, opts, scratch,
                     (size_t)BN_NOALLOC_SCRATCH_BYTES, stream);
+}
+
+int bn_network_set_persistent_launch(bn_network *net, int32_t lanes_per_cell,
+                                     int32_t slots_per_lane, int32_t waves_per_simd,
+                                     int32_t block_waves, double ms_per_cell) {
+  g_err.clear();
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (lanes_per_cell == 0) {
+    net->pL = net->pS = net->pW = net->pbw = 0;
+    return BN_SUCCESS;
+  }
+  if (waves_per_simd != 1 && waves_per_simd != 2)
+    return fail(BN_EINVAL, "waves_per_simd must be 1 or 2");
+  if ((waves_per_simd == 2 ? multi_shape_index(lanes_per_cell, slots_per_lane)
+                           : multi1_shape_index(lanes_per_cell, slots_per_lane)) < 0)
+    return fail(BN_EINVAL, "no persistent kernel with this shape at these waves per SIMD");
+  if (lanes_per_cell * slots_per_lane < net->n)
+    return fail(BN_EINVAL, "launch shape smaller than the system");
+  if (block_waves < 1 || block_waves > 4) return fail(BN_EINVAL, "block_waves must be 1..4");
+  net->pL = lanes_per_cell;
+  net->pS = slots_per_lane;
+  net->pW = waves_per_simd;
+  net->pbw = block_waves;
+  if (ms_per_cell > 0.0) net->ms_per_cell = ms_per_cell;
+  return BN_SUCCESS;
+}
+
+int bn_network_get_persistent_launch(const bn_network *net, int32_t *lanes_per_cell,
+                                     int32_t *slots_per_lane, int32_t *waves_per_simd,
+                                     int32_t *block_waves) {
+  g_err.clear();
+  if (!net || !lanes_per_cell || !slots_per_lane || !waves_per_simd || !block_waves)
+    return fail(BN_EINVAL, "null argument");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  const ItemLaunch l = item_launch(net, lim, 0);
+  *lanes_per_cell = l.L;
+  *slots_per_lane = l.S;
+  *waves_per_simd = l.W;
+  *block_waves = l.bw;
+  return BN_SUCCESS;
 }
 
 int bn_network_set_launch(bn_network *net, int32_t lanes_per_cell, int32_t slots_per_lane,
@@ -815,6 +893,137 @@ int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
   net->L = bL;
   net->S = bS;
   net->block_waves = bbw;
+  net->ms_per_cell = best / (double)n_cells;
+  return BN_SUCCESS;
+}
+
+
+int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const double *state,
+                                   const double *rho, const double *T, double dt, double rtol,
+                                   double atol, const double *log_mult, int32_t max_steps,
+                                   bn_persistent_tune_result *results, int32_t max_results,
+                                   int32_t *n_results, void *stream) {
+  g_err.clear();
+  if (n_results) *n_results = 0;
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (n_cells < 1) return fail(BN_EINVAL, "autotune needs at least one cell");
+  if (!state || !rho || !T) return fail(BN_EINVAL, "null state, rho or T");
+  if (int rc = check_tol(dt, rtol, atol)) return rc;
+  if (net->screened) return fail(BN_EUNSUPPORTED, "screened networks are not autotuned");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t ybytes = (size_t)net->N * n_cells * 8, tbytes = (size_t)n_cells * 8;
+  // the sample's working copies, then the ordered launch's workspace
+  bn_batch_item item{};
+  item.net = net;
+  item.n_cells = n_cells;
+  const size_t wsb = burn_batch_multi_order_workspace_bytes(1, &item);
+  const size_t o_ws = align256(ybytes + tbytes + (size_t)n_cells * 4);
+  void *scratch = nullptr;
+  if (hipMalloc(&scratch, o_ws + wsb) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BN_ENOMEM, "hipMalloc of the autotune scratch failed");
+  }
+  double *Ys = static_cast<double *>(scratch);
+  double *Ts = Ys + (size_t)net->N * n_cells;
+  int32_t *sts = reinterpret_cast<int32_t *>(Ts + n_cells);
+  void *ws = static_cast<char *>(scratch) + o_ws;
+  item.state = Ys;
+  item.rho = rho;
+  item.T = Ts;
+  item.log_mult = log_mult;
+  item.status = sts;
+  item.counters = nullptr;
+  bn_burn_opts o{};
+  o.max_steps = max_steps > 0 ? max_steps : 100000;
+  o.order_cells = 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = BN_SUCCESS;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = fail(BN_EHIP, "hipEventCreate failed");
+  const int saved[4] = {net->pL, net->pS, net->pW, net->pbw};
+  double best = -1.0;
+  int best_c[4] = {0, 0, 0, 0};
+  int nres = 0;
+  const int n = net->n;
+  for (int W = 2; W >= 1 && rc == BN_SUCCESS; --W) {
+    for (int si = 0; si < bn::N_MULTI_SHAPES && rc == BN_SUCCESS; ++si) {
+      const bn::ShapeLS sh = W == 2 ? bn::MULTI_SHAPES_2[si] : bn::MULTI_SHAPES_1[si];
+      const int NP = sh.L * sh.S;
+      if (NP < n || NP >= 4 * n + 16) continue;  // too small, or mostly padding
+      for (int bw = 1; bw <= 4 && rc == BN_SUCCESS; bw *= 2) {
+        if (lds_bytes(net->R, sh.L, sh.S, n, bw) > lim.lds_block) continue;
+        net->pL = sh.L;
+        net->pS = sh.S;
+        net->pW = W;
+        net->pbw = bw;
+        double ms = 0.0;
+        hipError_t e = hipSuccess;
+        int brc = BN_SUCCESS;
+        for (int rep = 0; rep < 2 && e == hipSuccess && brc == BN_SUCCESS; ++rep) {
+          // the first run warms up
+          if ((e = hipMemcpyAsync(Ys, state, ybytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+          if ((e = hipMemcpyAsync(Ts, T, tbytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
+          if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+          brc = multi_impl(1, &item, dt, rtol, atol, &o, ws, wsb, stream);
+          if (brc != BN_SUCCESS) break;
+          if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+          if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+          float f = 0.0f;
+          if ((e = hipEventElapsedTime(&f, e0, e1)) != hipSuccess) break;
+          ms = f;
+        }
+        const bool okrun = e == hipSuccess && brc == BN_SUCCESS;
+        if (results && nres < max_results) {
+          bn_persistent_tune_result &r = results[nres];
+          r.lanes_per_cell = sh.L;
+          r.slots_per_lane = sh.S;
+          r.waves_per_simd = W;
+          r.block_waves = bw;
+          r.status = okrun ? 0 : (brc != BN_SUCCESS ? brc : (int32_t)e);
+          r.ms = okrun ? ms : -1.0;
+        }
+        ++nres;
+        if (!okrun) {
+          if (brc == BN_EUNSUPPORTED) continue;  // does not fit: skipped
+          if (brc != BN_SUCCESS) {
+            rc = brc;
+            break;
+          }
+          rc = fail(BN_EHIP, std::string("autotune launch failed: ") + hipGetErrorString(e));
+          break;
+        }
+        if (best < 0.0 || ms < best) {
+          best = ms;
+          best_c[0] = sh.L;
+          best_c[1] = sh.S;
+          best_c[2] = W;
+          best_c[3] = bw;
+        }
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(scratch);
+  if (n_results) *n_results = std::min(nres, max_results > 0 ? max_results : 0);
+  if (rc != BN_SUCCESS || best < 0.0) {
+    net->pL = saved[0];
+    net->pS = saved[1];
+    net->pW = saved[2];
+    net->pbw = saved[3];
+    if (rc != BN_SUCCESS) return rc;
+    return fail(BN_EUNSUPPORTED, "no persistent launch fits this network");
+  }
+  net->pL = best_c[0];
+  net->pS = best_c[1];
+  net->pW = best_c[2];
+  net->pbw = best_c[3];
   net->ms_per_cell = best / (double)n_cells;
   return BN_SUCCESS;
 }

@@ -286,3 +286,53 @@ def test_synth50_full_size_sampled(gpu, oracle):
     out = gpu.burn_multi([(net, cells.Y, cells.rho, cells.T)], cfg.t_end, RTOL, ATOL)[0]
     _sampled(oracle, spec, cells, cfg.t_end, out, 256, 7)
     net.close()
+
+
+def test_persistent_autotune_cache_then_burn(gpu, oracle, tmp_path):
+    """Tune the persistent kernel on a sample (cache miss: every fitting
+    shape, waves-per-SIMD class and workgroup size timed), reload the choice
+    from the cache for a fresh handle of the same network (no timing), and
+    burn with it: parity with the oracle."""
+    cfg = synth.config(2, n_cells=8192)
+    spec, cells = cfg.networks[0], cfg.cells[0]
+    cache = str(tmp_path / "tune.json")
+    net = gpu.Network(spec)
+    e1 = gpu.tune_cached(net, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL, cache=cache)
+    assert not e1["hit"]
+    timed = [c for c in e1["candidates"] if c[4] is not None]
+    assert len(timed) >= 6
+    assert {c[2] for c in timed} == {1, 2}  # both waves-per-SIMD classes
+    choice = net.get_persistent_launch()
+    assert list(choice) == e1["persistent"]
+    best = min(timed, key=lambda c: c[4])
+    assert tuple(best[:4]) == choice
+    net2 = gpu.Network(spec)
+    e2 = gpu.tune_cached(net2, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL, cache=cache)
+    assert e2["hit"] and net2.get_persistent_launch() == choice
+    sub = cells.subset(np.arange(1500))
+    g = _host(gpu.burn_multi([(net2, sub.Y, sub.rho, sub.T)], cfg.t_end, RTOL, ATOL)[0])
+    _check(g, oracle, spec, sub, cfg.t_end)
+    net.close()
+    net2.close()
+
+
+def test_multi_launch_per_waves_class(gpu, oracle):
+    """Networks whose persistent choices are in different waves-per-SIMD
+    classes share one call (one launch per class): each result is bitwise
+    that of the network burned alone with its choice."""
+    cfg, cells = _mixed(n_cells=(600, 300, 200, 150))
+    nets = [gpu.Network(s) for s in cfg.networks]
+    nets[0].set_persistent_launch(16, 1, 2, 4)
+    nets[1].set_persistent_launch(16, 2, 1, 2)
+    nets[2].set_persistent_launch(64, 1, 2, 2)
+    nets[3].set_persistent_launch(64, 1, 1, 1)
+    outs = gpu.burn_multi([(n, c.Y, c.rho, c.T) for n, c in zip(nets, cells)], cfg.t_end,
+                          RTOL, ATOL)
+    for n, spec, c, out in zip(nets, cfg.networks, cells, outs):
+        g = _host(out)
+        alone = _host(gpu.burn_multi([(n, c.Y, c.rho, c.T)], cfg.t_end, RTOL, ATOL)[0])
+        for a, b in zip(g, alone):
+            assert np.array_equal(a, b, equal_nan=True)
+        _check(g, oracle, spec, c, cfg.t_end)
+    for n in nets:
+        n.close()
