@@ -520,8 +520,13 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
 
   // ---- right-hand side F = f(yv) for the own components; 1 if finite.
   // The group's lanes take the reactions r = q, q+L, ...; each rate is added
-  // into the accumulator of every species it changes (LDS atomics: lanes of
-  // one instruction add in lane order, i.e. in ascending reaction index).
+  // into the accumulator of every species it changes with LDS atomics, one
+  // instruction per entry slot of the reactions' species lists.  A species'
+  // terms are therefore summed slot by slot (every reaction for which it is
+  // the first listed species, then the second, ...), within a slot in lane
+  // order: not the ascending reaction order of the definition, so the sums
+  // round differently from a serial sum.  The heat term is a tree sum over
+  // the group's lanes times 1/c_v.
   auto rhs = [&]() __attribute__((always_inline)) -> int {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
