@@ -41,22 +41,25 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_body.h",
+KERNEL_SOURCES = ["paper_2312_02836_amd/csrc/burn_gen_body.h",
+                  "paper_2312_02836_amd/csrc/burn_gen_args.h",
+                  "paper_2312_02836_amd/csrc/burn_codegen.cpp",
+                  "paper_2312_02836_amd/csrc/burn_body.h",
                   "paper_2312_02836_amd/csrc/bn_math.h",
                   "paper_2312_02836_amd/csrc/burn_plain.h",
                   "paper_2312_02836_amd/csrc/burn_multi.hip",
                   "paper_2312_02836_amd/csrc/burn_internal.h"]
-TRAFFIC_FILE = "profiles/burn_multi_kernel__synth13_30__65536cells__hbm_traffic.txt"
-SQ_FILE = "profiles/burn_multi_kernel__synth13_30__65536cells__sq_counters.txt"
+TRAFFIC_FILE = "profiles/bn_gen_burn__synth13_30__65536cells__hbm_traffic.txt"
+SQ_FILE = "profiles/bn_gen_burn__synth13_30__65536cells__sq_counters.txt"
 
 WORKLOADS = {
-    "synth13": dict(config=2, cells=65536, mode="persistent",
+    "synth13": dict(config=2, cells=65536, mode="persistent", body="generated",
                     text="burn of one synthetic 13-species/30-reaction network, {cells} cells, "
                          "dt=1e-2, rtol 1e-6, atol 1e-10"),
     "robertson3": dict(config=1, cells=256, mode="plain",
                        text="plain burn of the Robertson-like 3-species/4-reaction network, "
                             "{cells} cells, t_end=1e3, rtol 1e-6, atol 1e-10"),
-    "mixed4": dict(config=4, cells=65536, mode="persistent",
+    "mixed4": dict(config=4, cells=65536, mode="persistent", body="generated",
                    text="mixed persistent burn, synthetic 13/30 + 21/60 + 35/100 + 50/150 "
                         "species/reaction networks, {cells} cells each in one launch, dt=1e-2, "
                         "rtol 1e-6, atol 1e-10"),
@@ -152,6 +155,20 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
         b["st"] = torch.empty(n_cells, dtype=torch.int32, device=dev)
         b["cnt"] = torch.empty((8, n_cells), dtype=torch.int32, device=dev)
         batches.append(b)
+    # the generated kernel where the workload asks for it and the system
+    # size allows (compiled, or taken from the cache, outside the timed region)
+    body = args.body if (args.body and wl_name == args.workload) else wl.get("body", "table")
+    gen = []
+    if body == "generated" and wl["mode"] != "adjoint":
+        for b in batches:
+            if b["spec"].n <= 16 and b["spec"].screen is None:
+                t0 = time.perf_counter()
+                lanes = b["net"].generate()
+                gen.append({"network": f"{b['spec'].n_species}/{b['spec'].n_reactions}",
+                            "lanes_per_cell": lanes,
+                            "seconds": round(time.perf_counter() - t0, 2)})
+                log(f"{wl_name}: generated kernel for {gen[-1]['network']}, {lanes} lanes per "
+                    f"cell ({gen[-1]['seconds']} s)")
     opts = _lib.BurnOpts(0, 0, args.block_waves, 0)
     # the persistent kernel's launch choice per network: from the tuning
     # cache, or tuned on the first 16,384 cells (outside the timed region)
@@ -223,7 +240,12 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
             f"{np.mean(kms):.3f} ms (min {min(kms):.3f})")
         return 1000.0 * wall / n_steps, float(np.mean(kms))
 
-    other = None
+    def set_body(name):
+        for b in batches:
+            if b["net"].body[1]:
+                b["net"].set_body(name)
+
+    other, table_pers = None, None
     if wl["mode"] == "plain":
         if compare:
             other = ("persistent",) + timed(step_persistent, "persistent", max(1, steps // 2), 1)
@@ -232,14 +254,24 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
         kernel_name = "burn_plain_kernel"
     else:
         if compare:
-            other = ("plain",) + timed(step_plain, "plain (one launch per network)",
+            # the table-driven kernels beside the generated one: plain
+            # launches, and the persistent launch when a network has a
+            # generated kernel
+            set_body("table")
+            other = ("plain",) + timed(step_plain, "plain table kernels (one launch per network)",
                                        max(1, min(steps, 5) // 2 if use_graph else steps),
                                        1 if use_graph else warmup)
+            if gen:
+                table_pers = timed(step_persistent, "persistent, table kernels only",
+                                   max(1, steps // 2), 1)
+            set_body("generated")
         ms_per_step, kernel_ms = timed(step_persistent,
                                        "persistent (graph replay)" if use_graph else
-                                       "persistent (one launch)", steps, warmup)
+                                       "persistent (one launch" +
+                                       (", generated kernels)" if gen else ")"), steps, warmup)
         outs = [(b["st_m"], b["cnt_m"]) for b in batches]
-        kernel_name = "burn_multi_kernel"
+        kernel_name = "bn_gen_burn" if gen and len(gen) == len(batches) else (
+            "bn_gen_burn + burn_multi_kernel" if gen else "burn_multi_kernel")
 
     n_ok, f_path, f_ext, step_stats = 0, 0.0, 0.0, []
     for b, (st, cnt) in zip(batches, outs):
@@ -268,7 +300,7 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
               "t_end": cfg.t_end, "kernel": kernel_name, "graph_replay": use_graph,
               "launch": [list(b["net"].get_launch()) for b in batches],
               "persistent_launch": [list(b["net"].get_persistent_launch()) for b in batches],
-              "persistent_tuning": tune,
+              "persistent_tuning": tune, "generated": gen,
               "steps_mean_p5_p95": step_stats}
     config[f"{'plain' if wl['mode'] == 'plain' else 'persistent'}_kernel_ms"] = kernel_ms
     if other is not None:
@@ -276,6 +308,9 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
         pers = kernel_ms if wl["mode"] == "persistent" else other[2]
         plain = kernel_ms if wl["mode"] == "plain" else other[2]
         config["persistent_vs_plain"] = plain / pers
+    if table_pers is not None:
+        config["table_persistent_kernel_ms"] = table_pers[1]
+        config["generated_vs_table_persistent"] = table_pers[1] / kernel_ms
     cpu = None
     if cpu_seconds > 0:
         cpu = cpu_baseline(batches, cfg, cpu_seconds, one_thread_seconds)
@@ -453,6 +488,8 @@ def main() -> int:
     ap.add_argument("--cells", type=int, default=0, help="cells per network (0 = workload's)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--block-waves", type=int, default=0)
+    ap.add_argument("--body", choices=["generated", "table"], default=None,
+                    help="kernels of the headline workload (default: the workload's)")
     ap.add_argument("--mode", choices=["plain", "persistent"], default=None,
                     help="override the workload's launch mode")
     ap.add_argument("--no-compare", action="store_true",
@@ -500,7 +537,7 @@ def main() -> int:
 
     if args.workload == "synth13" and head["roofline"]["kernel_ms"] > 0:
         default_launch = (not args.cells and not args.lanes and not args.block_waves
-                          and not args.mode)
+                          and not args.mode and args.body in (None, "generated"))
         tr = profile_values(TRAFFIC_FILE) if default_launch else None
         if tr is not None:
             head["roofline"]["traffic"] = float(tr["traffic_bytes_per_launch"])

@@ -244,6 +244,69 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
 int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double dt,
                              double rtol, double atol, const bn_burn_opts *opts, void *stream);
 
+/* ---- Generated per-network kernels ------------------------------------- */
+
+/* The paper generates the right-hand side and analytic Jacobian of each
+ * network as code (Sec. 2, "Arbitrary Network Generation").  These calls do
+ * the same for the burn: the library writes a HIP source in which the rates,
+ * the right-hand side and the Jacobian of one network are straight-line code
+ * (stoichiometry, rate coefficients and sparsity as compile-time constants;
+ * every sum in ascending reaction order, as in the definitions), compiles it
+ * for gfx950 at run time (hiprtc) together with the integrator, and launches
+ * it in place of the table-driven kernels.  The integrator, its decisions,
+ * statuses and counters are those of burn_batch.
+ *
+ * Layout of the generated body: a cell is owned by one lane (systems of up
+ * to 8 components) or a pair of lanes (up to 16): each lane keeps its rows of
+ * the LU factors in registers, with the fill pattern of I - cJ under diagonal
+ * pivots fixed at compile time, and checks at every column that partial
+ * pivoting chooses the diagonal; a cell whose factorization would pivot
+ * elsewhere finishes it with row interchanges in a per-lane scratch area
+ * (the pivots are always those of partial pivoting, first largest magnitude).
+ * One workgroup of four waves per compute unit; the cells come from a device
+ * queue as in burn_batch_multi. */
+#define BN_BODY_TABLE 0     /* the table-driven kernels (any network) */
+#define BN_BODY_GENERATED 1 /* the network's generated kernel */
+
+/* The generated source for a network (host only; no device needed).
+ *   lanes_per_cell  0 = automatic (1 up to 8 components, else 2 up to 16),
+ *                   or 1 or 2
+ * Writes at most cap bytes (NUL-terminated) into buf (may be NULL) and the
+ * full size including the NUL into *len (may be NULL).  BN_EUNSUPPORTED for
+ * screened networks and systems above 16 components. */
+int bn_codegen_source(const bn_network_desc *desc, int32_t lanes_per_cell, char *buf, size_t cap,
+                      size_t *len);
+
+/* Compile a network's generated kernel into the cache directory cache_dir
+ * (host only; no device needed), so that bn_network_generate finds it there.
+ * The cache file is named by a hash of the source, the integrator body, the
+ * compiler options and the compiler version.  BN_EHIP with the compiler log
+ * in bn_last_error if compilation fails. */
+int bn_codegen_prebuild(const bn_network_desc *desc, int32_t lanes_per_cell,
+                        const char *cache_dir);
+
+/* Generate, compile (or take from cache_dir, which may be NULL for no cache;
+ * a compiled kernel is written there when the directory is writable) and
+ * load the network's kernel on the network's device, allocate its
+ * workspaces (per lane of the launch grid: the Jacobian's nonzero rows and a
+ * pivoting scratch area of n^2 + 4n doubles; they belong to the network and
+ * are freed by bn_network_destroy) and select BN_BODY_GENERATED.  The
+ * device must be gfx950.  From then on burn_batch, burn_batch_ex (with
+ * lanes_per_cell 0) and burn_batch_multi use the generated kernel for this
+ * network; the sensitivity, source-term and screened calls keep the
+ * table-driven kernels.  Two launches of one generated network must not be
+ * in flight at once (they share its workspaces).  Compilation takes seconds;
+ * the call is synchronous. */
+int bn_network_generate(bn_network *net, int32_t lanes_per_cell, const char *cache_dir);
+
+/* Select the body a network's burns use: BN_BODY_TABLE, or
+ * BN_BODY_GENERATED (after bn_network_generate; else BN_EINVAL). */
+int bn_network_set_body(bn_network *net, int32_t body);
+
+/* The selected body, and the lanes per cell of the generated kernel (0 if
+ * there is none).  Either pointer may be NULL. */
+int bn_network_get_body(const bn_network *net, int32_t *body, int32_t *lanes_per_cell);
+
 /* ---- Launch-shape autotuner -------------------------------------------- */
 
 typedef struct {

@@ -27,7 +27,9 @@ EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "bn_network_set_persistent_launch", "bn_network_get_persistent_launch",
            "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
            "burn_batch_adjoint_backward", "burn_batch_adjoint", "burn_batch_sdc",
-           "bn_last_error", "bn_version"]
+           "bn_codegen_source", "bn_codegen_prebuild", "bn_network_generate",
+           "bn_network_set_body", "bn_network_get_body", "bn_last_error", "bn_version"]
+BODY_TABLE, BODY_GENERATED = 0, 1
 MAX_ITEMS = 8
 
 
@@ -37,6 +39,29 @@ class NetworkDesc(C.Structure):
                 ("products", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_double)),
                 ("q", C.POINTER(C.c_double)), ("c_v", C.c_double),
                 ("screen", C.POINTER(C.c_double))]
+
+
+def network_desc(spec):
+    """(NetworkDesc, arrays it points into) for a NetworkSpec; keep the
+    arrays alive while the descriptor is used."""
+    import numpy as np
+    arrays = [np.ascontiguousarray(spec.mass, dtype=np.int32),
+              np.ascontiguousarray(spec.reactants, dtype=np.int32),
+              np.ascontiguousarray(spec.products, dtype=np.int32),
+              np.ascontiguousarray(spec.coef, dtype=np.float64),
+              np.ascontiguousarray(spec.q, dtype=np.float64)]
+    m, rs, ps, cf, q = arrays
+    i32 = C.POINTER(C.c_int32)
+    f64 = C.POINTER(C.c_double)
+    scr = None
+    if spec.screen is not None:
+        scr = np.ascontiguousarray(spec.screen, dtype=np.float64)
+        arrays.append(scr)
+    desc = NetworkDesc(spec.n_species, spec.n_reactions, m.ctypes.data_as(i32),
+                       rs.ctypes.data_as(i32), ps.ctypes.data_as(i32), cf.ctypes.data_as(f64),
+                       q.ctypes.data_as(f64), spec.c_v,
+                       scr.ctypes.data_as(f64) if scr is not None else None)
+    return desc, arrays
 
 
 class BurnOpts(C.Structure):
@@ -136,6 +161,17 @@ def lib() -> C.CDLL:
     L.burn_batch_sdc.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double,
                                  dp, dp, ip, ip, C.POINTER(BurnOpts), vp]
     L.burn_batch_sdc.restype = C.c_int
+    L.bn_codegen_source.argtypes = [C.POINTER(NetworkDesc), C.c_int32, C.c_char_p, C.c_size_t,
+                                    C.POINTER(C.c_size_t)]
+    L.bn_codegen_source.restype = C.c_int
+    L.bn_codegen_prebuild.argtypes = [C.POINTER(NetworkDesc), C.c_int32, C.c_char_p]
+    L.bn_codegen_prebuild.restype = C.c_int
+    L.bn_network_generate.argtypes = [vp, C.c_int32, C.c_char_p]
+    L.bn_network_generate.restype = C.c_int
+    L.bn_network_set_body.argtypes = [vp, C.c_int32]
+    L.bn_network_set_body.restype = C.c_int
+    L.bn_network_get_body.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.bn_network_get_body.restype = C.c_int
     L.bn_last_error.restype = C.c_char_p
     L.bn_version.restype = C.c_char_p
     _lib = L

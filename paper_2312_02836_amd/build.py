@@ -14,7 +14,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libburn.so")
 
-SOURCES = ["burn_api.cpp", "burn_multi.hip", "burn_plain_p0.hip", "burn_plain_p1.hip",
+BUILD = os.path.join(HERE, "_build")
+
+SOURCES = ["burn_api.cpp", "burn_codegen.cpp", "burn_multi.hip", "burn_plain_p0.hip", "burn_plain_p1.hip",
            "burn_plain_p2.hip", "burn_adjoint.hip", "burn_sdc.hip",
            "burn_screen.hip"]
 
@@ -33,10 +35,34 @@ def hipcc() -> str:
     return "hipcc"
 
 
+# headers of the generated kernels' body, embedded in the library as text
+# (the per-network sources are compiled with them at run time)
+GEN_HEADERS = [("BNG_BODY_H", "burn_gen_body.h"), ("BNG_ARGS_H", "burn_gen_args.h")]
+
+
+def write_gen_headers() -> str:
+    """_build/burn_gen_headers.inc: each body header as a C string."""
+    os.makedirs(BUILD, exist_ok=True)
+    out = os.path.join(BUILD, "burn_gen_headers.inc")
+    parts = []
+    for name, fn in GEN_HEADERS:
+        with open(os.path.join(CSRC, fn)) as f:
+            text = f.read()
+        if ")BNGSRC\"" in text:
+            raise RuntimeError(fn + " contains the raw-string delimiter")
+        parts.append(f'static const char {name}[] = R"BNGSRC({text})BNGSRC";\n')
+    tmp = out + ".tmp"
+    with open(tmp, "w") as f:
+        f.write("".join(parts))
+    os.replace(tmp, out)
+    return out
+
+
 def build(verbose: bool = False) -> str:
     """Compile every source (in parallel, one object each) and link
     libburn.so (always recompiles)."""
-    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    write_gen_headers()
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", BUILD]
     with tempfile.TemporaryDirectory(prefix="burn_build_") as tmpd:
         objs, procs = [], []
         for src in SOURCES:
@@ -50,7 +76,8 @@ def build(verbose: bool = False) -> str:
         if failed:
             raise RuntimeError("hipcc failed on " + ", ".join(failed))
         tmp = LIB + ".tmp"
-        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp]
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + [
+            "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -25,25 +25,33 @@ class Network:
     def __init__(self, spec: NetworkSpec):
         spec.validate()
         self.spec = spec
-        self._arrays = [np.ascontiguousarray(spec.mass, dtype=np.int32),
-                        np.ascontiguousarray(spec.reactants, dtype=np.int32),
-                        np.ascontiguousarray(spec.products, dtype=np.int32),
-                        np.ascontiguousarray(spec.coef, dtype=np.float64),
-                        np.ascontiguousarray(spec.q, dtype=np.float64)]
-        m, rs, ps, cf, q = self._arrays
-        i32 = C.POINTER(C.c_int32)
-        f64 = C.POINTER(C.c_double)
-        scr = None
-        if spec.screen is not None:
-            scr = np.ascontiguousarray(spec.screen, dtype=np.float64)
-            self._arrays.append(scr)
-        desc = _lib.NetworkDesc(spec.n_species, spec.n_reactions, m.ctypes.data_as(i32),
-                                rs.ctypes.data_as(i32), ps.ctypes.data_as(i32),
-                                cf.ctypes.data_as(f64), q.ctypes.data_as(f64), spec.c_v,
-                                scr.ctypes.data_as(f64) if scr is not None else None)
+        desc, self._arrays = _lib.network_desc(spec)
         h = C.c_void_p()
         _lib.check(_lib.lib().bn_network_create(C.byref(desc), C.byref(h)), "bn_network_create")
         self.handle = h
+
+    def generate(self, lanes_per_cell: int = 0, cache_dir: Optional[str] = None) -> int:
+        """Compile (or take from the cache) and load the network's generated
+        kernel, and select it; returns its lanes per cell.  cache_dir
+        defaults to default_codegen_cache()."""
+        d = default_codegen_cache() if cache_dir is None else cache_dir
+        _lib.check(_lib.lib().bn_network_generate(self.handle, lanes_per_cell,
+                                                  d.encode() if d else None),
+                   "bn_network_generate")
+        return self.body[1]
+
+    def set_body(self, body: str) -> None:
+        """'table' or 'generated' (after generate())."""
+        code = {"table": _lib.BODY_TABLE, "generated": _lib.BODY_GENERATED}[body]
+        _lib.check(_lib.lib().bn_network_set_body(self.handle, code), "bn_network_set_body")
+
+    @property
+    def body(self) -> Tuple[str, int]:
+        """(selected body, lanes per cell of the generated kernel or 0)."""
+        b, l = C.c_int32(), C.c_int32()
+        _lib.check(_lib.lib().bn_network_get_body(self.handle, C.byref(b), C.byref(l)),
+                   "bn_network_get_body")
+        return ("generated" if b.value == _lib.BODY_GENERATED else "table"), l.value
 
     def set_launch(self, lanes_per_cell: int, slots_per_lane: int, block_waves: int = 0) -> None:
         """Fix the launch shape (0 lanes = back to the default)."""
@@ -305,6 +313,37 @@ def autotune_persistent(net: Network, Y, rho, T, dt: float, rtol: float = 1e-6,
     _lib.check(rc, "bn_network_autotune_persistent")
     return [(r.lanes_per_cell, r.slots_per_lane, r.waves_per_simd, r.block_waves,
              r.ms if r.status == 0 else None) for r in res[:nres.value]]
+
+
+def default_codegen_cache() -> str:
+    """Directory of compiled generated kernels: $BURN_CODEGEN_CACHE, else the
+    package's _codegen directory."""
+    return os.environ.get("BURN_CODEGEN_CACHE") or os.path.join(
+        os.path.dirname(os.path.abspath(__file__)), "_codegen")
+
+
+def codegen_source(spec: NetworkSpec, lanes_per_cell: int = 0) -> str:
+    """The HIP source the library generates for a network."""
+    desc, keep = _lib.network_desc(spec)
+    n = C.c_size_t()
+    _lib.check(_lib.lib().bn_codegen_source(C.byref(desc), lanes_per_cell, None, 0, C.byref(n)),
+               "bn_codegen_source")
+    buf = C.create_string_buffer(n.value)
+    _lib.check(_lib.lib().bn_codegen_source(C.byref(desc), lanes_per_cell, buf, n.value, None),
+               "bn_codegen_source")
+    del keep
+    return buf.value.decode()
+
+
+def codegen_prebuild(spec: NetworkSpec, lanes_per_cell: int = 0,
+                     cache_dir: Optional[str] = None) -> None:
+    """Compile a network's generated kernel into the cache (no GPU needed)."""
+    desc, keep = _lib.network_desc(spec)
+    d = default_codegen_cache() if cache_dir is None else cache_dir
+    os.makedirs(d, exist_ok=True)
+    _lib.check(_lib.lib().bn_codegen_prebuild(C.byref(desc), lanes_per_cell, d.encode()),
+               "bn_codegen_prebuild")
+    del keep
 
 
 def default_tune_cache() -> str:

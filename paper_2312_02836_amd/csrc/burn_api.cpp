@@ -13,7 +13,23 @@
 #include <string>
 #include <vector>
 
+#include "burn_codegen.h"
+#include "burn_gen_args.h"
 #include "burn_internal.h"
+
+// A network's generated kernel (bn_network_generate): the loaded module and
+// the per-lane workspaces of its launch grid.
+struct GenKernel {
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  int lpc = 0;              // lanes per cell
+  size_t lds = 0;           // dynamic LDS per workgroup
+  int grid = 0;             // workgroups (one per CU)
+  long long n_lanes = 0;    // grid threads
+  double *jws = nullptr;    // Jacobian rows [entries][n_lanes]
+  double *lws = nullptr;    // pivoting scratch [n*n + 4n][n_lanes]
+  unsigned long long *queue = nullptr;  // the unordered launch's counter
+};
 
 struct bn_network {
   int N = 0, R = 0, n = 0, nnz = 0;
@@ -28,6 +44,9 @@ struct bn_network {
   // and the LDS footprint)
   int pL = 0, pS = 0, pW = 0, pbw = 0;
   bool screened = false;
+  bn::GenDesc desc;         // host copy for code generation
+  GenKernel *gen = nullptr;
+  int body = BN_BODY_TABLE;
 };
 
 namespace {
@@ -145,6 +164,69 @@ bool pick_shape(const bn_network *net, int lanes_hint, int *L, int *S) {
 
 size_t lds_bytes(int R, int L, int S, int n, int bw) {
   return bn::table_lds_bytes(R) + (size_t)bw * bn::wave_lds_bytes(L, S, n);
+}
+
+void fill_desc(const bn_network_desc *d, bn::GenDesc *g) {
+  g->N = d->n_species;
+  g->R = d->n_reactions;
+  g->mass.assign(d->mass, d->mass + g->N);
+  g->reac.assign(d->reactants, d->reactants + 3 * g->R);
+  g->prod.assign(d->products, d->products + 3 * g->R);
+  g->coef.assign(d->coef, d->coef + 7 * g->R);
+  g->q.assign(d->q, d->q + g->R);
+  g->c_v = d->c_v;
+}
+
+void free_gen(GenKernel *g) {
+  if (!g) return;
+  if (g->mod) (void)hipModuleUnload(g->mod);
+  if (g->jws) (void)hipFree(g->jws);
+  if (g->lws) (void)hipFree(g->lws);
+  if (g->queue) (void)hipFree(g->queue);
+  delete g;
+}
+
+// lanes per cell of the generated body for a system of n components (0:
+// none supported), or check an explicit choice
+int gen_lanes(int n, int want) {
+  if (want == 1) return n <= bn::GEN_MAX_N1 ? 1 : 0;
+  if (want == 2) return n <= bn::GEN_MAX_N2 ? 2 : 0;
+  if (want != 0) return 0;
+  if (n <= bn::GEN_MAX_N1) return 1;
+  if (n <= bn::GEN_MAX_N2) return 2;
+  return 0;
+}
+
+// Launch the generated kernel over the cells of a (for an ordered launch:
+// staged) batch; parts = the XCD part counters, or null for the kernel's
+// own queue counter (reset here by a kernel).
+hipError_t launch_gen(const bn_network *net, const bn::BurnArgs &a, unsigned long long *queue,
+                      hipStream_t st) {
+  const GenKernel &g = *net->gen;
+  bng::GenArgs ga{};
+  ga.Y = a.Y;
+  ga.T = a.T;
+  ga.rho = a.rho;
+  ga.status = a.status;
+  ga.counters = a.counters;
+  ga.log_mult = a.log_mult;
+  ga.jws = g.jws;
+  ga.lws = g.lws;
+  ga.queue = queue;
+  ga.parts = a.parts;
+  ga.n_cells = a.n_cells;
+  ga.n_lanes = g.n_lanes;
+  ga.t_end = a.t_end;
+  ga.rtol = a.rtol;
+  ga.atol = a.atol;
+  ga.max_steps = a.max_steps;
+  if (!a.parts) {
+    const hipError_t e = bn::launch_zero(queue, 1, st);
+    if (e != hipSuccess) return e;
+  }
+  void *params[] = {&ga};
+  return hipModuleLaunchKernel(g.fn, (unsigned)g.grid, 1, 1, 256, 1, 1, (unsigned)g.lds, st, params,
+                               nullptr);
 }
 
 int check_tol(double dt, double rtol, double atol) {
@@ -335,6 +417,7 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
   t.screen = d->screen ? reinterpret_cast<const double *>(base + o_scr) : nullptr;
   t.wsq = reinterpret_cast<const double *>(base + o_wsq);
   net->screened = d->screen != nullptr;
+  fill_desc(d, &net->desc);
   *out = net;
   return BN_SUCCESS;
 }
@@ -342,6 +425,7 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
 void bn_network_destroy(bn_network *net) {
   if (!net) return;
   if (net->dev) (void)hipFree(net->dev);
+  free_gen(net->gen);
   delete net;
 }
 
@@ -388,6 +472,12 @@ int burn_batch_ex(const bn_network *net, int64_t n_cells, double *state, const d
   a.atol = atol;
   a.max_steps = o.max_steps;
 
+  if (net->body == BN_BODY_GENERATED && !o.lanes_per_cell) {
+    const hipError_t e = launch_gen(net, a, net->gen->queue, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+      return fail(BN_EHIP, std::string("generated kernel launch failed: ") + hipGetErrorString(e));
+    return BN_SUCCESS;
+  }
   if (net->screened && multi_shape_index(L, S) < 0) {
     if (o.lanes_per_cell)
       return fail(BN_EUNSUPPORTED, "a screened network runs with 8, 16, 32 or 64 lanes per cell");
@@ -541,6 +631,7 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     bn::BurnArgs a;
     ItemLaunch l;
     double cost;
+    const bn_network *net;
   };
   std::vector<It> its;
   for (int j = 0; j < n_items; ++j) {
@@ -554,6 +645,7 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     if (!x.state || !x.rho || !x.T)
       return fail(BN_EINVAL, "null state, rho or T in item " + std::to_string(j));
     It it{};
+    it.net = x.net;
     it.l = item_launch(x.net, lim, o.block_waves);
     if (it.l.shape < 0) return fail(BN_EUNSUPPORTED, "no persistent kernel shape for item " +
                                                          std::to_string(j));
@@ -586,10 +678,14 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
                                : "workspace missing or smaller than burn_batch_multi_workspace_bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 8)
     return fail(BN_EINVAL, "workspace must be 8-byte aligned");
-  // two-wave class first, each class costliest network first (its cells then
-  // start first and the tail is made of cheap ones)
-  std::stable_sort(its.begin(), its.end(), [](const It &x, const It &y) {
-    if (x.l.W != y.l.W) return x.l.W > y.l.W;
+  // Generated networks first (each its own launch), then the two-wave class,
+  // then the one-wave class; each class costliest network first (its cells
+  // then start first and the tail is made of cheap ones).
+  auto klass = [](const It &x) {
+    return x.net->body == BN_BODY_GENERATED ? 0 : (x.l.W == 2 ? 1 : 2);
+  };
+  std::stable_sort(its.begin(), its.end(), [&](const It &x, const It &y) {
+    if (klass(x) != klass(y)) return klass(x) < klass(y);
     return x.cost > y.cost;
   });
 
@@ -629,10 +725,17 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
       staged[j] = s;
     }
   }
+  // the generated networks' launches
+  size_t g0 = 0;
+  for (; g0 < its.size() && klass(its[g0]) == 0; ++g0) {
+    e = launch_gen(its[g0].net, staged[g0], queue + g0, st);
+    if (e != hipSuccess)
+      return fail(BN_EHIP, std::string("generated kernel launch failed: ") + hipGetErrorString(e));
+  }
   // one persistent launch per class
-  for (size_t c0 = 0; c0 < its.size();) {
+  for (size_t c0 = g0; c0 < its.size();) {
     size_t c1 = c0;
-    while (c1 < its.size() && its[c1].l.W == its[c0].l.W) ++c1;
+    while (c1 < its.size() && klass(its[c1]) == klass(its[c0])) ++c1;
     const int W = its[c0].l.W;
     bn::MultiArgs m{};
     m.n_items = (int)(c1 - c0);
@@ -712,6 +815,128 @@ int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double
                              hipGetErrorString(e));
   return multi_impl(n_items, items, dt, rtol, atol, opts, scratch,
                     (size_t)BN_NOALLOC_SCRATCH_BYTES, stream);
+}
+
+namespace {
+int gen_desc_check(const bn_network_desc *d) {
+  if (!d) return fail(BN_EINVAL, "null network description");
+  const int N = d->n_species, R = d->n_reactions;
+  if (N < 1 || R < 1 || !d->mass || !d->reactants || !d->products || !d->coef || !d->q)
+    return fail(BN_EINVAL, "incomplete network description");
+  if (R > BN_MAX_REACTIONS) return fail(BN_EUNSUPPORTED, "n_reactions exceeds BN_MAX_REACTIONS");
+  for (int r = 0; r < 3 * R; ++r)
+    if (d->reactants[r] < -1 || d->reactants[r] >= N || d->products[r] < -1 || d->products[r] >= N)
+      return fail(BN_EINVAL, "species index out of range");
+  if (!(d->c_v > 0.0) || !std::isfinite(d->c_v)) return fail(BN_EINVAL, "c_v must be positive");
+  if (d->screen) return fail(BN_EUNSUPPORTED, "the generated body has no screening");
+  return BN_SUCCESS;
+}
+}  // namespace
+
+int bn_codegen_source(const bn_network_desc *desc, int32_t lanes_per_cell, char *buf, size_t cap,
+                      size_t *len) {
+  g_err.clear();
+  if (int rc = gen_desc_check(desc)) return rc;
+  const int lpc = gen_lanes(desc->n_species + 1, lanes_per_cell);
+  if (!lpc) return fail(BN_EUNSUPPORTED, "no generated body for this system size and lanes_per_cell");
+  bn::GenDesc g;
+  fill_desc(desc, &g);
+  const std::string src = bn::gen_source(g, lpc);
+  if (len) *len = src.size() + 1;
+  if (buf && cap) {
+    const size_t m = std::min(cap - 1, src.size());
+    std::memcpy(buf, src.data(), m);
+    buf[m] = '\0';
+  }
+  return BN_SUCCESS;
+}
+
+int bn_codegen_prebuild(const bn_network_desc *desc, int32_t lanes_per_cell,
+                        const char *cache_dir) {
+  g_err.clear();
+  if (int rc = gen_desc_check(desc)) return rc;
+  if (!cache_dir || !*cache_dir) return fail(BN_EINVAL, "cache_dir is required");
+  const int lpc = gen_lanes(desc->n_species + 1, lanes_per_cell);
+  if (!lpc) return fail(BN_EUNSUPPORTED, "no generated body for this system size and lanes_per_cell");
+  bn::GenDesc g;
+  fill_desc(desc, &g);
+  std::vector<char> code;
+  std::string err;
+  if (bn::gen_build(g, lpc, cache_dir, &code, &err) != 0) return fail(BN_EHIP, err);
+  return BN_SUCCESS;
+}
+
+int bn_network_generate(bn_network *net, int32_t lanes_per_cell, const char *cache_dir) {
+  g_err.clear();
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (net->screened) return fail(BN_EUNSUPPORTED, "the generated body has no screening");
+  const int lpc = gen_lanes(net->n, lanes_per_cell);
+  if (!lpc) return fail(BN_EUNSUPPORTED, "no generated body for this system size and lanes_per_cell");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(BN_EHIP, "hipGetDevice failed");
+  if (dev != net->device) return fail(BN_EINVAL, "network was created on another device");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(BN_EHIP, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(BN_EUNSUPPORTED, std::string("generated kernels are built for gfx950, not ") +
+                                     prop.gcnArchName);
+  DeviceLimits lim;
+  if (int rc = device_limits(dev, &lim)) return rc;
+  const size_t lds = bn::gen_lds_bytes(net->desc, lpc);
+  if (lds > lim.lds_block)
+    return fail(BN_EUNSUPPORTED, "the generated body's LDS exceeds a workgroup's");
+  std::vector<char> code;
+  std::string err;
+  if (bn::gen_build(net->desc, lpc, cache_dir ? cache_dir : "", &code, &err) != 0)
+    return fail(BN_EHIP, err);
+  auto *g = new GenKernel();
+  g->lpc = lpc;
+  g->lds = lds;
+  g->grid = lim.cus;
+  g->n_lanes = (long long)lim.cus * 256;
+  const int n = net->n;
+  const size_t jb = (size_t)bn::gen_entries(net->desc, lpc) * g->n_lanes * sizeof(double);
+  const size_t lb = (size_t)(n * n + 4 * n) * g->n_lanes * sizeof(double);
+  if (hipModuleLoadData(&g->mod, code.data()) != hipSuccess) {
+    free_gen(g);
+    (void)hipGetLastError();
+    return fail(BN_EHIP, "hipModuleLoadData of the generated kernel failed");
+  }
+  if (hipModuleGetFunction(&g->fn, g->mod, "bn_gen_burn") != hipSuccess) {
+    free_gen(g);
+    (void)hipGetLastError();
+    return fail(BN_EHIP, "the generated code object has no bn_gen_burn");
+  }
+  if (hipMalloc(&g->jws, jb) != hipSuccess || hipMalloc(&g->lws, lb) != hipSuccess ||
+      hipMalloc(&g->queue, 256) != hipSuccess) {
+    free_gen(g);
+    (void)hipGetLastError();
+    return fail(BN_ENOMEM, "hipMalloc of the generated kernel's workspaces failed");
+  }
+  free_gen(net->gen);
+  net->gen = g;
+  net->body = BN_BODY_GENERATED;
+  return BN_SUCCESS;
+}
+
+int bn_network_set_body(bn_network *net, int32_t body) {
+  g_err.clear();
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (body != BN_BODY_TABLE && body != BN_BODY_GENERATED)
+    return fail(BN_EINVAL, "body must be BN_BODY_TABLE or BN_BODY_GENERATED");
+  if (body == BN_BODY_GENERATED && !net->gen)
+    return fail(BN_EINVAL, "the network has no generated kernel (bn_network_generate)");
+  net->body = body;
+  return BN_SUCCESS;
+}
+
+int bn_network_get_body(const bn_network *net, int32_t *body, int32_t *lanes_per_cell) {
+  g_err.clear();
+  if (!net) return fail(BN_EINVAL, "null network");
+  if (body) *body = net->body;
+  if (lanes_per_cell) *lanes_per_cell = net->gen ? net->gen->lpc : 0;
+  return BN_SUCCESS;
 }
 
 int bn_network_set_persistent_launch(bn_network *net, int32_t lanes_per_cell,
