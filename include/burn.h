@@ -358,7 +358,9 @@ typedef struct {
  * waves per workgroup) on a sample of cells, each as an ordered
  * burn_batch_multi launch of the sample alone, and make the fastest the
  * network's persistent choice (and its time per cell the network's cost
- * estimate).  The caller's arrays are only read.  Synchronizes `stream`;
+ * estimate).  The candidates are the table-driven kernel's: a network whose
+ * generated kernel is selected is timed with the table body and keeps its
+ * selection.  The caller's arrays are only read.  Synchronizes `stream`;
  * allocates device memory; not for use under graph capture.
  *   state, rho, T  DEVICE sample in the burn_batch layout (n_cells >= 1)
  *   results        HOST [max_results] or NULL; *n_results = entries written

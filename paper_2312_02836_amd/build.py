@@ -37,7 +37,8 @@ def hipcc() -> str:
 
 # headers of the generated kernels' body, embedded in the library as text
 # (the per-network sources are compiled with them at run time)
-GEN_HEADERS = [("BNG_BODY_H", "burn_gen_body.h"), ("BNG_ARGS_H", "burn_gen_args.h")]
+GEN_HEADERS = [("BNG_BODY_H", "burn_gen_body.h"), ("BNG_ARGS_H", "burn_gen_args.h"),
+               ("BNG_MATH_H", "bn_math.h")]
 
 
 def write_gen_headers() -> str:

@@ -21,9 +21,13 @@
 // the host and the device evaluate it identically.
 #pragma once
 
+// (also compiled at run time with the generated kernels, where hiprtc
+// provides the runtime and math declarations itself)
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#endif
 
 namespace bn {
 

@@ -29,6 +29,11 @@ struct GenKernel {
   double *jws = nullptr;    // Jacobian rows [entries][n_lanes]
   double *lws = nullptr;    // pivoting scratch [n*n + 4n][n_lanes]
   unsigned long long *queue = nullptr;  // the unordered launch's counter
+  // factorization batching of the wave (see the kernel's pass): a pass runs
+  // once lu_batch cells want one or a cell has waited lu_wait iterations
+  // (8 and 3 measured best on the 13/30 launch, 19.5 ms against 22.1 ms for
+  // a pass whenever any cell wants one; results are bitwise the same)
+  int lu_batch = 8, lu_wait = 3;
 };
 
 struct bn_network {
@@ -220,6 +225,8 @@ hipError_t launch_gen(const bn_network *net, const bn::BurnArgs &a, unsigned lon
   ga.rtol = a.rtol;
   ga.atol = a.atol;
   ga.max_steps = a.max_steps;
+  ga.lu_batch = g.lu_batch;
+  ga.lu_wait = g.lu_wait;
   if (!a.parts) {
     const hipError_t e = bn::launch_zero(queue, 1, st);
     if (e != hipSuccess) return e;
@@ -1171,6 +1178,11 @@ int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const doubl
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     rc = fail(BN_EHIP, "hipEventCreate failed");
   const int saved[4] = {net->pL, net->pS, net->pW, net->pbw};
+  // the choices tuned are the table-driven persistent kernel's: a network
+  // with its generated kernel selected is timed with the table body and
+  // given its selection back at the end
+  const int saved_body = net->body;
+  net->body = BN_BODY_TABLE;
   double best = -1.0;
   int best_c[4] = {0, 0, 0, 0};
   int nres = 0;
@@ -1236,6 +1248,7 @@ int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const doubl
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(st);
   (void)hipFree(scratch);
+  net->body = saved_body;
   if (n_results) *n_results = std::min(nres, max_results > 0 ? max_results : 0);
   if (rc != BN_SUCCESS || best < 0.0) {
     net->pL = saved[0];

@@ -29,7 +29,7 @@
 namespace bn {
 namespace {
 
-#include "burn_gen_headers.inc"  // BNG_BODY_H, BNG_ARGS_H: the two headers' text
+#include "burn_gen_headers.inc"  // BNG_BODY_H, BNG_ARGS_H, BNG_MATH_H: the headers' text
 
 std::string hexd(double v) {
   char buf[64];
@@ -123,12 +123,33 @@ std::string gen_source(const GenDesc &d, int lpc) {
     << " reactions, " << lpc << " lane(s) per cell.\n";
   o << "#include \"burn_gen_body.h\"\nnamespace bng {\nstruct GenNet {\n";
   o << "  static constexpr int N = " << N << ", R = " << R << ", n = " << n << ";\n";
-  o << "  static constexpr int NS = " << NS << ";\n";
+  o << "  static constexpr int NS = " << NS << ", RB = " << (R + 7) / 8 * 8 << ";\n";
   o << "  static constexpr unsigned long long fpat[n] = {";
   for (int i = 0; i < n; ++i) o << (i ? ", " : "") << "0x" << std::hex << fp[i] << std::dec << "ull";
   o << "};\n  static constexpr unsigned long long ufill[NS] = {";
   for (int s = 0; s < NS; ++s) o << (s ? ", " : "") << "0x" << std::hex << ufp[s] << std::dec << "ull";
   o << "};\n";
+  // the heat row's quotients by c_v: q = x (1/c_v), then Markstein's
+  // correction step, which gives the correctly rounded x / c_v wherever that
+  // is a normal number (a non-finite x gives a non-finite result, which every
+  // caller treats alike)
+  o << "  static constexpr double cv = " << hexd(d.c_v) << ", icv = " << hexd(1.0 / d.c_v) << ";\n";
+  o << "  __device__ __forceinline__ static double div_cv(double x) {\n"
+       "    const double q = x * icv;\n    return fma(fma(-q, cv, x), icv, q);\n  }\n";
+  const int RT = (R + lpc - 1) / lpc;  // rate exponentials per lane
+  if (lpc > 1) {
+    // the rate coefficients as a table that the kernel copies into the LDS:
+    // the lanes of a cell evaluate different reactions' exponentials (lane h
+    // takes reactions t * lpc + h), each reading its own coefficients;
+    // padding rows are zero
+    o << "  static constexpr int RT = " << RT << ";\n";
+    o << "  static constexpr double ctab[" << RT * lpc * 8 << "] = {";
+    for (int r = 0; r < RT * lpc; ++r)
+      for (int j = 0; j < 8; ++j)
+        o << ((r || j) ? ", " : "") << ((r < R && j < 7) ? hexd(d.coef[7 * r + j]) : std::string("0.0"));
+    o << "};\n";
+  }
+  o << "  static constexpr long long HOST_LDS = " << gen_lds_bytes(d, lpc) << ";\n";
 
   // T powers, as in the rate definition
   const char *tpow =
@@ -136,7 +157,7 @@ std::string gen_source(const GenDesc &d, int lpc) {
       "    const double t13 = cbrt(T);\n"
       "    const double tm13 = 1.0 / t13;\n"
       "    const double t53 = T * t13 * t13;\n"
-      "    const double lnT = log(T);\n"
+      "    const double lnT = bn::bn_log(T);\n"
       "    const double tinv = 1.0 / T;\n";
   auto lam_expr = [&](int r) {
     const double *a = d.coef.data() + 7 * r;
@@ -145,6 +166,26 @@ std::string gen_source(const GenDesc &d, int lpc) {
       << hexd(a[3]) << " * t13 + " << hexd(a[4]) << " * T + " << hexd(a[5]) << " * t53 + "
       << hexd(a[6]) << " * lnT) * em[" << r << "]";
     return e.str();
+  };
+  // the exponentials l<r> of every reaction, in every lane of the cell
+  // (with several lanes per cell each lane evaluates its share, read from
+  // the LDS table at em + RB, and broadcasts it)
+  auto emit_lams = [&](const char *ind) {
+    if (lpc == 1) {
+      for (int r = 0; r < R; ++r) o << ind << "const double l" << r << " = " << lam_expr(r) << ";\n";
+      return;
+    }
+    o << ind << "double lo[RT];\n" << ind << "{\n"
+      << ind << "  const double *ct = em + RB + h * 8;\n"
+      << ind << "#pragma unroll\n" << ind << "  for (int t = 0; t < RT; ++t) {\n"
+      << ind << "    const double2 *c = (const double2 *)(ct + t * " << lpc * 8 << ");\n"
+      << ind << "    const double2 c01 = c[0], c23 = c[1], c45 = c[2], c6 = c[3];\n"
+      << ind << "    lo[t] = exp(c01.x + c01.y * tinv + c23.x * tm13 + c23.y * t13 + c45.x * T + "
+                "c45.y * t53 + c6.x * lnT) * em[t * " << lpc << " + h];\n"
+      << ind << "  }\n" << ind << "}\n";
+    for (int r = 0; r < R; ++r)
+      o << ind << "const double l" << r << " = Grp<" << lpc << ">::template bcast<" << r % lpc
+        << ">(lo[" << r / lpc << "]);\n";
   };
   // prefactor lambda / prod m! rho^(n_r - 1)
   auto pre_expr = [&](int r) {
@@ -176,12 +217,12 @@ std::string gen_source(const GenDesc &d, int lpc) {
   o << tpow;
   // every sum starts at 0 and takes its terms in ascending reaction order,
   // each rate as soon as it is formed
+  emit_lams("    ");
   o << "    double e = 0.0";
   for (int i = 0; i < N; ++i) o << ", f" << i << " = 0.0";
   o << ";\n";
   for (int r = 0; r < R; ++r) {
-    o << "    {\n      const double l" << r << " = " << lam_expr(r) << ";\n";
-    o << "      const double p" << r << " = " << pre_expr(r) << ";\n";
+    o << "    {\n      const double p" << r << " = " << pre_expr(r) << ";\n";
     o << "      const double r" << r << " = " << rate_expr(r) << ";\n";
     for (int i = 0; i < N; ++i) {
       const int v = nu_of(d, i, r);
@@ -191,7 +232,7 @@ std::string gen_source(const GenDesc &d, int lpc) {
   }
   std::vector<std::string> fexpr(n);
   for (int i = 0; i < N; ++i) fexpr[i] = "f" + std::to_string(i);
-  o << "    const double f" << N << " = e / " << hexd(d.c_v) << ";\n";
+  o << "    const double f" << N << " = div_cv(e);\n";
   fexpr[N] = "f" + std::to_string(N);
   for (int s = 0; s < NS; ++s) {
     std::vector<std::string> vals(lpc);
@@ -222,10 +263,8 @@ std::string gen_source(const GenDesc &d, int lpc) {
        "int &jbad) {\n"
        "#pragma clang fp contract(off)\n";
   o << tpow;
-  for (int r = 0; r < R; ++r) {
-    o << "    const double l" << r << " = " << lam_expr(r) << ";\n";
-    o << "    const double p" << r << " = " << pre_expr(r) << ";\n";
-  }
+  emit_lams("    ");
+  for (int r = 0; r < R; ++r) o << "    const double p" << r << " = " << pre_expr(r) << ";\n";
   // One column at a time: its terms (one per reactant slot holding the
   // species, the product of the other slots; the temperature column last,
   // dR/dT = R d ln lambda / dT), then the own entries of that column.
@@ -264,7 +303,7 @@ std::string gen_source(const GenDesc &d, int lpc) {
         }
         std::string &e = Jc[N];
         if (e.empty()) e = "0.0";
-        e = "(" + e + " + " + hexd(d.q[r]) + " * " + nm + " / " + hexd(d.c_v) + ")";
+        e = "(" + e + " + div_cv(" + hexd(d.q[r]) + " * " + nm + "))";
       }
     emit_column(j, Jc);
     o << "    }\n";
@@ -288,7 +327,7 @@ std::string gen_source(const GenDesc &d, int lpc) {
       }
       std::string &e = Jc[N];
       if (e.empty()) e = "0.0";
-      e = "(" + e + " + " + hexd(d.q[r]) + " * dT" + std::to_string(r) + " / " + hexd(d.c_v) + ")";
+      e = "(" + e + " + div_cv(" + hexd(d.q[r]) + " * dT" + std::to_string(r) + "))";
     }
     emit_column(N, Jc);
     o << "    }\n";
@@ -336,12 +375,15 @@ int gen_entries(const GenDesc &d, int lpc) {
 
 size_t gen_lds_bytes(const GenDesc &d, int lpc) {
   const int n = d.N + 1, NS = (n + lpc - 1) / lpc;
-  const size_t rb = (size_t)(d.R + 7) / 8 * 8;
-  // four waves of [rows][NS][64]: the history (7 rows), psi and the
-  // reciprocal scales, and the Newton correction and reciprocal pivots when
-  // they fit in the LDS of a compute unit
-  const size_t full = 8 * (rb + (size_t)4 * 11 * NS * 64);
-  return full <= 160 * 1024 ? full : 8 * (rb + (size_t)4 * 9 * NS * 64);
+  // the rate multipliers (rounded up to 8), the coefficient table when the
+  // lanes of a cell split the rates, then four waves of [rows][NS][64]: the
+  // history (7 rows), psi and the reciprocal scales, and the Newton
+  // correction and reciprocal pivots when they fit in the LDS of a compute
+  // unit.  The generated source carries this size and the kernel checks at
+  // compile time that its own layout needs exactly this much.
+  const size_t head = (size_t)(d.R + 7) / 8 * 8 + (lpc > 1 ? (size_t)(d.R + lpc - 1) / lpc * lpc * 8 : 0);
+  const size_t full = 8 * (head + (size_t)4 * 11 * NS * 64);
+  return full <= 160 * 1024 ? full : 8 * (head + (size_t)4 * 9 * NS * 64);
 }
 
 const std::vector<std::string> &gen_options() {
@@ -363,6 +405,7 @@ uint64_t gen_key(const std::string &src) {
   mix(src.data(), src.size());
   mix(BNG_BODY_H, sizeof(BNG_BODY_H));
   mix(BNG_ARGS_H, sizeof(BNG_ARGS_H));
+  mix(BNG_MATH_H, sizeof(BNG_MATH_H));
   for (const std::string &s : gen_options()) mix(s.data(), s.size() + 1);
   int major = 0, minor = 0;
   if (hiprtcVersion(&major, &minor) == HIPRTC_SUCCESS) {
@@ -399,9 +442,9 @@ void gen_cache_write(const std::string &dir, const std::string &path, const std:
 
 int gen_compile(const std::string &src, std::vector<char> *code, std::string *log) {
   hiprtcProgram prog;
-  const char *hdrs[2] = {BNG_BODY_H, BNG_ARGS_H};
-  const char *names[2] = {"burn_gen_body.h", "burn_gen_args.h"};
-  if (hiprtcCreateProgram(&prog, src.c_str(), "bn_gen_burn.hip", 2, hdrs, names) != HIPRTC_SUCCESS) {
+  const char *hdrs[3] = {BNG_BODY_H, BNG_ARGS_H, BNG_MATH_H};
+  const char *names[3] = {"burn_gen_body.h", "burn_gen_args.h", "bn_math.h"};
+  if (hiprtcCreateProgram(&prog, src.c_str(), "bn_gen_burn.hip", 3, hdrs, names) != HIPRTC_SUCCESS) {
     *log = "hiprtcCreateProgram failed";
     return -1;
   }

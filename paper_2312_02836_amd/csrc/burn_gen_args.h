@@ -21,6 +21,8 @@ struct GenArgs {
   long long n_lanes;              // grid threads (the workspaces' lane stride)
   double t_end, rtol, atol;
   int max_steps;
+  int lu_batch;                   // a factorization pass runs once this many cells want one
+  int lu_wait;                    // ... or once a cell has waited this many iterations
   int pad_;
 };
 

@@ -11,9 +11,11 @@
 //
 // Mapping onto a 64-wide wavefront.  A cell is owned by LPC lanes (1 or 2):
 // component i lives on lane i % LPC, slot i / LPC (NS = ceil(n / LPC) slots
-// per lane).  Both lanes of a pair evaluate every rate (the generated code is
-// the same for both, so the wave stays converged) and each keeps its own
-// components of the right-hand side and its own rows of the Newton matrix.
+// per lane).  The lanes of a cell split the rate exponentials (lane h takes
+// reactions t LPC + h, its coefficients read from an LDS table) and
+// broadcast them; the rest of the generated code is the same in every lane
+// (so the wave stays converged), and each lane keeps its own components of
+// the right-hand side and its own rows of the Newton matrix.
 // Per lane:
 //   * registers: the entries of its LU rows that the fill pattern allows
 //     (the others are zero constants), their reciprocal pivots, and the
@@ -39,6 +41,7 @@
 // pivots are the ones partial pivoting chooses.
 #pragma once
 
+#include "bn_math.h"
 #include "burn_gen_args.h"
 
 namespace bng {
@@ -56,11 +59,21 @@ constexpr int DROWS = KMAX + 2;  // D_0 .. D_{k+1}; D_{k+2} is formed and used a
 constexpr int ROW_PSI = DROWS, ROW_ISC = DROWS + 1, ROW_DD = DROWS + 2, ROW_DINV = DROWS + 3;
 constexpr int LDS_BYTES = 160 * 1024;
 
+// Doubles at the head of the LDS: the rate multipliers (R rounded up to 8),
+// then, when the LPC lanes of a cell split the rate exponentials, the rate
+// coefficient table (8 per reaction, reactions padded to a multiple of LPC).
+constexpr int head_doubles(int R, int LPC) {
+  return (R + 7) / 8 * 8 + (LPC > 1 ? (R + LPC - 1) / LPC * LPC * 8 : 0);
+}
 // rows per slot in LDS for a system with NS slots and R reactions: the
 // Newton correction and the reciprocal pivots go there too when four waves
 // of it fit (it frees registers for the right-hand side)
-constexpr int lds_rows(int NS, int R) {
-  return (8 * ((R + 7) / 8 * 8 + 4 * (DROWS + 4) * NS * 64) <= LDS_BYTES) ? DROWS + 4 : DROWS + 2;
+constexpr int lds_rows(int NS, int R, int LPC) {
+  return (8 * (head_doubles(R, LPC) + 4 * (DROWS + 4) * NS * 64) <= LDS_BYTES) ? DROWS + 4
+                                                                                : DROWS + 2;
+}
+constexpr long long lds_bytes(int NS, int R, int LPC) {
+  return 8LL * (head_doubles(R, LPC) + 4LL * lds_rows(NS, R, LPC) * NS * 64);
 }
 constexpr int XCD_PARTS = 8;
 
@@ -80,6 +93,18 @@ constexpr double u_of(int i, int j) {
   double v = 1.0;
   for (int m = 1; m <= i; ++m) v *= (double)(m - 1 - j) / (double)m;
   return v;
+}
+
+// 1 / d from the hardware estimate and two Newton steps (within about one
+// unit in the last place; used where the quotient only scales a norm or
+// forms an LU multiplier, never where the integrator's definition fixes a
+// correctly rounded result).  d = 0 gives NaN, as does d = inf.
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
 }
 
 // x / d for a small positive integer d with r = 1 / d rounded: the product,
@@ -227,7 +252,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
   };
 
   // ---- per-lane state
-  constexpr bool VEC_LDS = lds_rows(NS, NET::R) == DROWS + 4;
+  constexpr bool VEC_LDS = lds_rows(NS, NET::R, LPC) == DROWS + 4;
   double LU[NS][n];  // rows comp(s) of the factors (diagonal pivots)
   double dinv_r[VEC_LDS ? 1 : NS], dd_r[VEC_LDS ? 1 : NS];  // when not in LDS
   double yv[NS], F[NS];
@@ -467,7 +492,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
       constexpr unsigned long long prow = NET::fpat[K];
       const double dg = G::template bcast<kh>(LU[ks][K]);
       if (!(fabs(dg) > 0.0)) fsing = 1;
-      const double rinv = 1.0 / dg;
+      const double rinv = rcp_nr(dg);
       if (!above(ks, K) && !below(ks, K)) dinv(ks) = rinv;
       double P[n];
 #pragma unroll
@@ -557,6 +582,8 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
   int status = 0, write_state = 0;
   int n_eq = 0, jac_cur = 0, lu_ok = 0, it = 0, need_attempt = 0, new_step = 0;
   int fresh_newton = 0, first_jac = 0;
+  int have_f = 0;     // F holds the waiting cell's first Newton RHS (1 finite, 2 not)
+  int lu_waited = 0;  // iterations this cell has waited for its factorization
   double t = 0.0, hs = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, err = 0.0, h0 = 0.0, d1 = 0.0;
 
   auto write_out = [&]() __attribute__((always_inline)) {
@@ -596,6 +623,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
     write_state = 0;
     k = 1;
     n_eq = jac_cur = lu_ok = it = need_attempt = new_step = fresh_newton = first_jac = 0;
+    have_f = lu_waited = 0;
     jr_ok = yj_pred = 0;
     t = hs = t_new = cc = dprev = err = h0 = d1 = 0.0;
 #pragma unroll
@@ -699,7 +727,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
             for (int j = 1; j <= KMAX; ++j)
               if (j <= k) sb += gamma_of(j) * Dref(j, s);
             Dref(ROW_PSI, s) = sb * igk;
-            Dref(ROW_ISC, s) = 1.0 / (atol + rtol * fabs(sa));
+            Dref(ROW_ISC, s) = rcp_nr(atol + rtol * fabs(sa));
             dd(s) = 0.0;
             yv[s] = sa;
           }
@@ -713,11 +741,29 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
     }
 
     // ---------------- B: factorizations ----------------
+    // A pass costs the wave about the same for one cell as for all of them,
+    // so a cell that wants a factorization may wait while the other cells
+    // step on: the pass runs once lu_batch cells want one, once a cell has
+    // waited lu_wait iterations, or when no other cell has work.  A waiting
+    // cell meanwhile evaluates its first Newton RHS (at the predictor, which
+    // the wait leaves unchanged); its own arithmetic is the same whether it
+    // waits or not.
     const int want = (phase == PH_NEWTON && fresh_newton && !lu_ok);
+    int run = 0;
+    {
+      const unsigned long long wmask = __ballot(want);
+      if (wmask != 0) {
+        const int others =
+            __ballot((phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !want) != 0;
+        run = !others || __popcll(wmask) >= (unsigned)(a.lu_batch * LPC) ||
+              __ballot(want && lu_waited >= a.lu_wait) != 0;
+      }
+    }
+    const int fac = want && run;
     int sing = 0;
-    if (__ballot(want) != 0) {
+    if (run) {
       int jbad = 0;
-      const int asmj = want && !jr_ok;
+      const int asmj = fac && !jr_ok;
       if (__ballot(asmj) != 0) {
         if (asmj) {
           // J(y_J) for the cells whose Jacobian was refreshed: into the
@@ -731,11 +777,11 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
           jr_ok = 1;
         }
       }
-      if (__ballot(want && !asmj) != 0) {
-        if (want && !asmj) NET::load_m(h, cc, LU, opaque(jws), stride());
+      if (__ballot(fac && !asmj) != 0) {
+        if (fac && !asmj) NET::load_m(h, cc, LU, opaque(jws), stride());
       }
       int dev = 0;
-      if (want) {
+      if (fac) {
         factor_diag(dev, sing);
         perm = 0;
       }
@@ -748,7 +794,8 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
           perm = 1;
         }
       }
-      if (want) {
+      if (fac) {
+        lu_waited = 0;
         if (first_jac && jbad) {
           // the Jacobian at the initial state is not finite
           status = ST_NONFINITE;
@@ -764,19 +811,39 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
 
     double pend = 0.0;
     // a singular Newton matrix is a failed Newton attempt (no RHS needed)
-    int nfail = (want && phase == PH_NEWTON && sing) ? 1 : 0;
-    fresh_newton = 0;
+    int nfail = (fac && phase == PH_NEWTON && sing) ? 1 : 0;
+    // a waiting cell's RHS that its factorization made moot (a singular
+    // matrix, or a non-finite Jacobian at the initial state) was never part
+    // of the integration
+    if (fac && have_f && (nfail || phase != PH_NEWTON)) {
+      cnt[CNT_RHS]--;
+      have_f = 0;
+    }
+    const int waiting = want && !run;
+    if (waiting) lu_waited++;
+    else fresh_newton = 0;
 
     // ---------------- C: right-hand side ----------------
-    const int active = (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail;
+    const int active =
+        (phase == PH_F0 || phase == PH_F1 || phase == PH_NEWTON) && !nfail && !have_f;
     int okf = 1;
     if (active) {
       okf = rhs();
       cnt[CNT_RHS]++;
     }
+    // what the RHS is used for now: not by a waiting cell, which keeps it
+    // for its factorization; a cell whose factorization ran takes the F it
+    // kept
+    int proceed = active && !waiting;
+    if (waiting && active) have_f = okf ? 1 : 2;
+    if (fac && have_f) {
+      proceed = 1;
+      okf = have_f == 1;
+      have_f = 0;
+    }
 
     // ---------------- D: what the new right-hand side is used for ----------------
-    if (active) {
+    if (proceed) {
       if (phase == PH_F0) {
         if (!okf) {
           status = ST_NONFINITE;
@@ -892,12 +959,12 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             const double aa = fabs(Dref(0, s)), bb = fabs(yv[s]);
-            isc[s] = 1.0 / (atol + rtol * (aa > bb ? aa : bb));
+            isc[s] = rcp_nr(atol + rtol * (aa > bb ? aa : bb));
             e1[s] = divq(dd(s), (double)(k + 1), rk1);
           }
           err = wrms(e1, isc);
           if (err > 1.0) {
-            double fct = kSafety * exp(log(err) * (-1.0 / (double)(k + 1)));
+            double fct = kSafety * exp(bn::bn_log(err) * (-1.0 / (double)(k + 1)));
             if (fct < kMinFactor) fct = kMinFactor;
             hs *= fct;
             pend = fct;
@@ -944,9 +1011,9 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
                   (k < KMAX) ? sqrt(divq(ep_acc, (double)n, 1.0 / (double)n)) : __builtin_inf();
               // the factors norm^(-1/(order+1)) of orders k-1, k, k+1,
               // compared by their logarithms; one exponential for the best
-              const double lm = log(em_n) * (-1.0 / (double)k);
-              const double l0 = log(err) * (-1.0 / (double)(k + 1));
-              const double lp = log(ep_n) * (-1.0 / (double)(k + 2));
+              const double lm = bn::bn_log(em_n) * (-1.0 / (double)k);
+              const double l0 = bn::bn_log(err) * (-1.0 / (double)(k + 1));
+              const double lp = bn::bn_log(ep_n) * (-1.0 / (double)(k + 2));
               double best = l0;
               int dk = 0;
               if (lm > best) {
@@ -1004,19 +1071,26 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
   }
 }
 
-// The kernel body: rate multipliers into LDS, then one wave per SIMD burns
-// cells from the queue.  LDS: em[R rounded up to 8] then per wave the rows
-// of lds_rows(NS, R), [rows][NS][64].
+// The kernel body: rate multipliers (and the coefficient table) into LDS,
+// then one wave per SIMD burns cells from the queue.  LDS: the head
+// (head_doubles), then per wave the rows of lds_rows, [rows][NS][64].
 template <class NET, int LPC>
 __device__ __forceinline__ void burn_kernel_body(const GenArgs &a) {
   constexpr int NS = (NET::n + LPC - 1) / LPC;
   constexpr int RB = (NET::R + 7) / 8 * 8;
+  constexpr int HEAD = head_doubles(NET::R, LPC);
+  // the launch's dynamic LDS (computed by the host) is what this layout uses
+  static_assert(lds_bytes(NS, NET::R, LPC) == NET::HOST_LDS, "LDS layout differs from the host's");
+  static_assert(NET::RB == RB, "multiplier block size");
   extern __shared__ double smem[];
-  for (int r = threadIdx.x; r < NET::R; r += blockDim.x)
-    smem[r] = a.log_mult ? exp(a.log_mult[r]) : 1.0;
+  for (int r = threadIdx.x; r < RB; r += blockDim.x)
+    smem[r] = r < NET::R ? (a.log_mult ? exp(a.log_mult[r]) : 1.0) : 1.0;
+  if constexpr (LPC > 1) {
+    for (int i = threadIdx.x; i < HEAD - RB; i += blockDim.x) smem[RB + i] = NET::ctab[i];
+  }
   __syncthreads();
   const int wave = threadIdx.x >> 6;
-  double *Dw = smem + RB + (long long)wave * lds_rows(NS, NET::R) * NS * 64;
+  double *Dw = smem + HEAD + (long long)wave * lds_rows(NS, NET::R, LPC) * NS * 64;
   run_cells<NET, LPC>(a, smem, Dw);
 }
 
