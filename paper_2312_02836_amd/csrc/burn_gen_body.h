@@ -303,15 +303,19 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
     }
   };
 
-  // weighted RMS norm over the n components (inv = 1 / scale)
-  auto wrms = [&](const double(&v)[NS], const double(&inv)[NS]) __attribute__((always_inline)) {
+  // weighted mean square over the n components (inv = 1 / scale), and its
+  // square root, the weighted RMS norm
+  auto wms = [&](const double(&v)[NS], const double(&inv)[NS]) __attribute__((always_inline)) {
     double acc = 0.0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const double z = v[s] * inv[s];
       if (real(s)) acc += z * z;
     }
-    return sqrt(divq(G::sum(acc), (double)n, 1.0 / (double)n));
+    return divq(G::sum(acc), (double)n, 1.0 / (double)n);
+  };
+  auto wrms = [&](const double(&v)[NS], const double(&inv)[NS]) __attribute__((always_inline)) {
+    return sqrt(wms(v, inv));
   };
 
   // change of step size by ratio rh on rows 0..k of D: D <- (R(rh) U)^T D.
@@ -578,13 +582,14 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
 
   // ================= cell state machine =================
   long long cell = -1;
+  int spent = 0;  // XCD parts of the queue this lane found exhausted (bit x)
   int phase = PH_LOAD;
   int status = 0, write_state = 0;
   int n_eq = 0, jac_cur = 0, lu_ok = 0, it = 0, need_attempt = 0, new_step = 0;
   int fresh_newton = 0, first_jac = 0;
   int have_f = 0;     // F holds the waiting cell's first Newton RHS (1 finite, 2 not)
   int lu_waited = 0;  // iterations this cell has waited for its factorization
-  double t = 0.0, hs = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, err = 0.0, h0 = 0.0, d1 = 0.0;
+  double t = 0.0, hs = 0.0, t_new = 0.0, cc = 0.0, dprev = 0.0, h0 = 0.0, d1 = 0.0;
 
   auto write_out = [&]() __attribute__((always_inline)) {
     // the rows' offsets from an opaque count, so they are formed here and not
@@ -625,7 +630,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
     n_eq = jac_cur = lu_ok = it = need_attempt = new_step = fresh_newton = first_jac = 0;
     have_f = lu_waited = 0;
     jr_ok = yj_pred = 0;
-    t = hs = t_new = cc = dprev = err = h0 = d1 = 0.0;
+    t = hs = t_new = cc = dprev = h0 = d1 = 0.0;
 #pragma unroll
     for (int c8 = 0; c8 < 8; ++c8) cnt[c8] = 0;
 #pragma unroll
@@ -669,9 +674,11 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
             const long long per = C / XCD_PARTS, extra = C % XCD_PARTS;
             for (int tt = 0; tt < XCD_PARTS && got < 0; ++tt) {
               const int x = (x0 + tt) % XCD_PARTS;
+              if ((spent >> x) & 1) continue;  // a part seen exhausted stays so
               const long long count = per + (x < extra ? 1 : 0);
               const unsigned long long i = atomicAdd(&a.parts[x], 1ULL);
               if ((long long)i < count) got = x * per + (x < extra ? x : extra) + (long long)i;
+              else spent |= 1 << x;
             }
           }
           got = __builtin_bit_cast(long long, G::template bcast<0>(__builtin_bit_cast(double, got)));
@@ -962,9 +969,12 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
             isc[s] = rcp_nr(atol + rtol * (aa > bb ? aa : bb));
             e1[s] = divq(dd(s), (double)(k + 1), rk1);
           }
-          err = wrms(e1, isc);
-          if (err > 1.0) {
-            double fct = kSafety * exp(bn::bn_log(err) * (-1.0 / (double)(k + 1)));
+          // err = sqrt(ms) is the error norm; the test err > 1 is taken
+          // exactly on ms (the correctly rounded square root exceeds 1
+          // exactly when ms exceeds 1 + 2^-52), and log err as (log ms) / 2
+          const double ms = wms(e1, isc);
+          if (ms > 0x1.0000000000001p+0) {
+            double fct = kSafety * exp(0.5 * bn::bn_log(ms) * (-1.0 / (double)(k + 1)));
             if (fct < kMinFactor) fct = kMinFactor;
             hs *= fct;
             pend = fct;
@@ -1005,15 +1015,17 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
             if (n_eq >= k + 1) {
               em_acc = G::sum(em_acc);
               ep_acc = G::sum(ep_acc);
-              const double em_n =
-                  (k > 1) ? sqrt(divq(em_acc, (double)n, 1.0 / (double)n)) : __builtin_inf();
-              const double ep_n =
-                  (k < KMAX) ? sqrt(divq(ep_acc, (double)n, 1.0 / (double)n)) : __builtin_inf();
+              // mean squares of the neighbouring orders' estimates
+              const double em_s =
+                  (k > 1) ? divq(em_acc, (double)n, 1.0 / (double)n) : __builtin_inf();
+              const double ep_s =
+                  (k < KMAX) ? divq(ep_acc, (double)n, 1.0 / (double)n) : __builtin_inf();
               // the factors norm^(-1/(order+1)) of orders k-1, k, k+1,
-              // compared by their logarithms; one exponential for the best
-              const double lm = bn::bn_log(em_n) * (-1.0 / (double)k);
-              const double l0 = bn::bn_log(err) * (-1.0 / (double)(k + 1));
-              const double lp = bn::bn_log(ep_n) * (-1.0 / (double)(k + 2));
+              // compared by their logarithms (log norm = (log ms) / 2); one
+              // exponential for the best
+              const double lm = 0.5 * bn::bn_log(em_s) * (-1.0 / (double)k);
+              const double l0 = 0.5 * bn::bn_log(ms) * (-1.0 / (double)(k + 1));
+              const double lp = 0.5 * bn::bn_log(ep_s) * (-1.0 / (double)(k + 2));
               double best = l0;
               int dk = 0;
               if (lm > best) {
