@@ -460,7 +460,10 @@ def run_adjoint(steps: int, warmup: int, n_cells: int, cpu_seconds: float) -> di
             "config": {"workload": wl["text"].format(cells=n_cells), "cells": n_cells,
                        "networks": [f"{spec.n_species}/{spec.n_reactions}"], "t_end": cfg.t_end,
                        "kernel": "adjoint_kernel (+ burn_record_kernel)", "forward_ms": fwd_ms,
-                       "backward_ms": bwd_ms, "max_steps": 1024},
+                       "backward_ms": bwd_ms, "max_steps": 1024,
+                       "workspace_bytes": int(run.ws.numel()),
+                       "workspace_min_bytes": int(run.ws_min),
+                       "state_pool_steps": int(run.pool_steps)},
             "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                          "traffic": None, "kernel_ms": kernel_ms,

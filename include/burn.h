@@ -394,9 +394,11 @@ int bn_network_get_persistent_launch(const bn_network *net, int32_t *lanes_per_c
  * step's order, step size and history rescale ratio, and the replay solves
  * every corrector exactly (full Newton to a weighted increment <= 1e-10).
  * The replay's end state is what the forward call returns; it agrees with
- * burn_batch's to the integrator's Newton tolerance.  The reverse sweep keeps
- * a checkpoint of the history every 16 accepted steps and recomputes each
- * segment.
+ * burn_batch's to the integrator's Newton tolerance.  The reverse sweep needs
+ * the corrected state of every replayed step: from a pool in the workspace
+ * where the replay kept them, or else recomputed segment by segment from a
+ * checkpoint of the history taken every 16 accepted steps (the same doubles
+ * either way, so the gradients do not depend on the pool's size).
  *
  * Workspace: caller-provided DEVICE memory of
  * burn_batch_adjoint_workspace_bytes(net, n_cells, max_steps) bytes, 8-byte
@@ -405,9 +407,15 @@ int bn_network_get_persistent_launch(const bn_network *net, int32_t *lanes_per_c
  * one 16-step segment for the reverse sweep, and the order in which the
  * replay and the reverse sweep take the cells (most recorded steps first,
  * so that the cells sharing a wave have similar step counts; 12 bytes per
- * cell); the forward call fills it,
- * the backward call reads it (same net, cells, dt, tolerances, log_mult and
- * max_steps), and it must not be shared by calls in flight.
+ * cell, and 8 bytes per cell for the pool offsets); the forward call fills
+ * it, the backward call reads it (same net, cells, dt, tolerances, log_mult,
+ * max_steps and workspace_bytes), and it must not be shared by calls in
+ * flight.  Bytes beyond that minimum are the pool of corrected states: the
+ * replay keeps the states of the cells that fit there (in cell index order,
+ * 8 (N + 1) bytes per accepted step) and the reverse sweep then skips their
+ * recomputation.  burn_batch_adjoint_states_bytes(net, S) is the pool that
+ * holds S accepted steps; the accepted steps of a batch are the sum over its
+ * OK cells of counter 0 of a previous forward call.
  * max_steps (1 .. 1,000,000) bounds the accepted steps of a cell; a cell that
  * needs more ends with BN_CELL_MAX_STEPS and a zero gradient.
  * Networks with more than BN_ADJOINT_MAX_REACTIONS reactions are not
@@ -416,6 +424,10 @@ int bn_network_get_persistent_launch(const bn_network *net, int32_t *lanes_per_c
 
 size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells,
                                           int32_t max_steps);
+
+/* Bytes of a pool of corrected states for total_steps accepted steps
+ * (8 (N + 1) total_steps), to append to the minimum workspace. */
+size_t burn_batch_adjoint_states_bytes(const bn_network *net, int64_t total_steps);
 
 /* Forward: recording run plus replay.
  *   state0, T0  DEVICE [N][n_cells], [n_cells]  initial state (read only)

@@ -25,7 +25,8 @@ EXPORTS = ["bn_network_create", "bn_network_destroy", "bn_network_n_species",
            "burn_batch_multi", "burn_batch_multi_noalloc", "bn_network_autotune",
            "bn_network_set_launch", "bn_network_get_launch", "bn_network_autotune_persistent",
            "bn_network_set_persistent_launch", "bn_network_get_persistent_launch",
-           "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_forward",
+           "burn_batch_adjoint_workspace_bytes", "burn_batch_adjoint_states_bytes",
+           "burn_batch_adjoint_forward",
            "burn_batch_adjoint_backward", "burn_batch_adjoint", "burn_batch_sdc",
            "bn_codegen_source", "bn_codegen_prebuild", "bn_network_generate",
            "bn_network_set_body", "bn_network_get_body", "bn_last_error", "bn_version"]
@@ -146,6 +147,8 @@ def lib() -> C.CDLL:
     L.bn_network_get_launch.restype = C.c_int
     L.burn_batch_adjoint_workspace_bytes.argtypes = [vp, C.c_int64, C.c_int32]
     L.burn_batch_adjoint_workspace_bytes.restype = C.c_size_t
+    L.burn_batch_adjoint_states_bytes.argtypes = [vp, C.c_int64]
+    L.burn_batch_adjoint_states_bytes.restype = C.c_size_t
     L.burn_batch_adjoint_forward.argtypes = [vp, C.c_int64, dp, dp, dp, C.c_double, C.c_double,
                                              C.c_double, dp, C.c_int32, dp, dp, dp, ip, ip, ip,
                                              vp, C.c_size_t, vp]

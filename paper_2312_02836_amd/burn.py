@@ -392,11 +392,16 @@ class AdjointRun:
     cell's schedule and replays it (end state, released energy E), then
     ``backward(gY, gE)`` returns the per-cell gradients [R, C] of
     sum_i gY_i Y_i + gE E with respect to the log-rate multipliers.  The
-    workspace (schedules and checkpoints) is allocated here, from torch."""
+    workspace (schedules, checkpoints and a pool of corrected states) is
+    allocated here, from torch.  The pool starts with room for
+    ``states_steps`` accepted steps (None: none) and grows at the start of a
+    forward call to the steps the previous one recorded, so that repeated
+    runs of one batch replay every cell from the pool; cells that do not
+    fit are recomputed from checkpoints (same gradients)."""
 
     def __init__(self, net: Network, Y0, rho, T0, dt: float, rtol: float = 1e-6,
                  atol: float = 1e-10, log_mult=None, *, max_steps: int = 2048,
-                 device: Optional[torch.device] = None):
+                 states_steps: Optional[int] = None, device: Optional[torch.device] = None):
         device = device or torch.device("cuda", torch.cuda.current_device())
         self.net, self.dt, self.rtol, self.atol = net, float(dt), float(rtol), float(atol)
         self.max_steps = int(max_steps)
@@ -407,8 +412,10 @@ class AdjointRun:
         if self.Y0.shape != (net.n_species, self.C) or self.T0.shape != (self.C,):
             raise ValueError("shapes of Y0, rho, T0 do not match")
         self.lm = None if log_mult is None else _dev_f64(log_mult, device)
-        nb = _lib.lib().burn_batch_adjoint_workspace_bytes(net.handle, self.C, self.max_steps)
-        self.ws = torch.empty(max(nb, 8), dtype=torch.uint8, device=device)
+        self.ws_min = _lib.lib().burn_batch_adjoint_workspace_bytes(net.handle, self.C,
+                                                                    self.max_steps)
+        self.ws = None
+        self._pool(int(states_steps or 0), device)
         self.Y = torch.empty_like(self.Y0)
         self.T = torch.empty_like(self.T0)
         self.E = torch.empty_like(self.T0)
@@ -421,7 +428,25 @@ class AdjointRun:
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
 
+    def _pool(self, steps: int, device) -> None:
+        """(Re)allocate the workspace with a pool for `steps` accepted steps."""
+        self.pool_steps = steps
+        nb = self.ws_min + _lib.lib().burn_batch_adjoint_states_bytes(self.net.handle, steps)
+        self.ws = None
+        self.ws = torch.empty(max(nb, 8), dtype=torch.uint8, device=device)
+
+    def recorded_steps(self) -> int:
+        """Accepted steps of the cells the last forward call finished (a
+        device synchronisation)."""
+        ok = self.status == 0
+        return int(self.counters[0][ok].sum().item())
+
     def forward(self):
+        if getattr(self, "_ran", False):
+            need = self.recorded_steps()
+            if need > self.pool_steps:
+                self._pool(need, self.device)
+        self._ran = True
         rc = _lib.lib().burn_batch_adjoint_forward(
             self.net.handle, self.C, _ptr(self.Y0), _ptr(self.rho), _ptr(self.T0), self.dt,
             self.rtol, self.atol, _ptr(self.lm), self.max_steps, _ptr(self.Y), _ptr(self.T),

@@ -22,9 +22,13 @@
 // transposes of the predictor, psi and the rescale.
 //
 // Memory: the schedule, a checkpoint of D every CK steps and the corrected
-// states of one CK-step segment live in a caller-provided workspace; the
-// reverse sweep recomputes each segment forward from its checkpoint, keeping
-// its corrected states, and walks it backwards.
+// states of one CK-step segment live in a caller-provided workspace.  When
+// the workspace also holds a pool for the corrected states (its size from
+// the recorded step counts), the replay keeps every cell's states there that
+// fit, and the reverse sweep reads them; for the other cells it recomputes
+// each segment forward from its checkpoint, keeping its corrected states, and
+// walks it backwards.  Either way the states are the same doubles (the same
+// replay arithmetic from the same history), so the gradients are too.
 //
 // Mapping: a cell per group of 32 lanes (two per wave) for systems of up to
 // 32 components, else a whole wave; lane i of the group = component i.  The
@@ -216,6 +220,10 @@ adjoint_kernel(AdjArgs a) {
   const double *sr = blk + 2 + a.sched_cap;
   const int32_t *so = reinterpret_cast<const int32_t *>(blk + 2 + 2 * (int64_t)a.sched_cap);
   double *ck = a.ckpt + (size_t)cell * a.n_ckpt * 7 * n;
+  // this cell's corrected states in the pool ([step][n]), or none
+  const int64_t so_off = a.soff ? a.soff[cell] : -1;
+  const bool has_states = so_off >= 0 && valid;
+  double *yst = has_states ? a.states + so_off : nullptr;
 
   // every slot starts with a valid pivot order and a finite state, so that
   // the group operations a resting cell takes part in stay in bounds
@@ -540,6 +548,7 @@ adjoint_kernel(AdjArgs a) {
       }
       const int okm = replay_step(m, act, y_new);
       if (act && !okm) ok = 0;
+      if (act && has_states && own) yst[(size_t)m * n + i] = y_new;
     }
     if (!dead) {
       if (i == 0 && a.iters) {
@@ -606,14 +615,15 @@ adjoint_kernel(AdjArgs a) {
     for (int sg = sg_end - 1; sg >= 0; --sg) {
       const int m0 = sg * CK;
       const int m1 = sg < n_seg ? (m0 + CK < nst ? m0 + CK : nst) : m0;
-      // recompute the segment from its checkpoint, keeping y_new
-      if (m1 > m0 && own) {
+      // recompute the segment from its checkpoint, keeping y_new (cells
+      // whose states the replay kept in the pool skip it)
+      if (m1 > m0 && own && !has_states) {
         const double *cp = ck + (size_t)sg * 7 * n;
 #pragma unroll
         for (int j = 0; j < DROWS; ++j) D[j] = cp[j * n + i];
       }
       for (int mm = 0; mm < CK; ++mm) {
-        const bool act = m0 + mm < m1;
+        const bool act = m0 + mm < m1 && !has_states;
         if (__ballot(act) == 0) break;  // later steps of the segment: no cell has them
         double y_new;
         replay_step(m0 + mm, act, y_new);
@@ -624,7 +634,8 @@ adjoint_kernel(AdjArgs a) {
         const int m = m0 + mm;
         const bool act = m < m1;
         if (__ballot(act) == 0) continue;
-        const double ys = (act && own) ? segg[mm * n + i] : 1.0;
+        const double ys = (act && own) ? (has_states ? yst[(size_t)m * n + i] : segg[mm * n + i])
+                                       : 1.0;
         const int k = act ? so[m] : 1;
         const double ratio = act ? sr[m] : 1.0;
         double gk = 1.0;
@@ -723,6 +734,39 @@ __global__ void __launch_bounds__(256) adj_key_kernel(AdjArgs a, float *key) {
                                                 : __builtin_inff();
 }
 
+// Exclusive scan of the cells' state counts (n * recorded steps, 0 for a
+// failed recording) in one workgroup: each thread sums a contiguous chunk,
+// the workgroup scans the chunk sums in LDS, then each thread writes its
+// chunk's offsets (-1 past the pool's capacity).
+__global__ void __launch_bounds__(1024) adj_states_kernel(AdjArgs a) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t C = a.n_cells, n = a.net.n;
+  const int64_t per = (C + 1023) / 1024;
+  const int64_t c0 = t * per < C ? t * per : C, c1 = c0 + per < C ? c0 + per : C;
+  auto count = [&](int64_t c) -> int64_t {
+    const double ns = a.sched[c * a.sched_stride];
+    return (ns > 0.0 && a.status[c] == ST_OK) ? n * (int64_t)ns : 0;
+  };
+  int64_t sum = 0;
+  for (int64_t c = c0; c < c1; ++c) sum += count(c);
+  part[t] = sum;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 chunk sums
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t off = part[t] - sum;
+  for (int64_t c = c0; c < c1; ++c) {
+    const int64_t k = count(c);
+    a.soff[c] = (k > 0 && off + k <= a.states_cap) ? off : -1;
+    off += k;
+  }
+}
+
 __global__ void __launch_bounds__(256) adj_inverse_kernel(const int32_t *pos, int64_t n,
                                                           int32_t *order) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -772,6 +816,12 @@ hipError_t launch_adjoint_order(const AdjArgs &a, float *key, int32_t *pos, unsi
   e = launch_sort_keys(key, n, pos, hist, stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(adj_inverse_kernel, dim3(blocks), dim3(256), 0, stream, pos, n, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_states(const AdjArgs &a, hipStream_t stream) {
+  if (a.n_cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adj_states_kernel, dim3(1), dim3(1024), 0, stream, a);
   return hipGetLastError();
 }
 

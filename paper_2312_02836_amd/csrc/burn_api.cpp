@@ -1276,11 +1276,14 @@ struct AdjLayout {
   int n_ckpt;
   size_t sched_bytes, ckpt_bytes, seg_bytes;
   size_t o_key, o_pos, o_order, o_hist;  // the cell order (costliest first)
-  size_t total;
+  size_t o_soff;                         // per cell, its states' offset in the pool
+  size_t total;                          // the minimum; a pool of states may follow
 };
 
 // schedules, checkpoints, the reverse sweep's segment states, then the cell
-// order's sort keys, positions, order and bucket counters (256-byte aligned)
+// order's sort keys, positions, order and bucket counters, the cells' state
+// offsets (256-byte aligned); what the caller's workspace holds beyond this
+// is the pool of corrected states
 AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
   AdjLayout l{};
   l.stride = bn::adjoint_sched_stride(cap);
@@ -1297,6 +1300,8 @@ AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
   o += align256(4 * (size_t)n_cells);
   l.o_hist = o;
   o += align256(8 * (size_t)bn::ORDER_BUCKETS);
+  l.o_soff = o;
+  o += align256(8 * (size_t)n_cells);
   l.total = o;
   return l;
 }
@@ -1330,7 +1335,7 @@ int adj_check(const bn_network *net, int64_t n_cells, double dt, double rtol, do
 bn::AdjArgs adj_args(const bn_network *net, int64_t n_cells, const double *state0,
                      const double *rho, const double *T0, double rtol, double atol,
                      const double *log_mult, int32_t max_steps, int32_t *status,
-                     void *workspace) {
+                     void *workspace, size_t workspace_bytes) {
   const AdjLayout l = adj_layout(net, n_cells, max_steps);
   bn::AdjArgs a{};
   a.net = net->tables;
@@ -1348,6 +1353,9 @@ bn::AdjArgs adj_args(const bn_network *net, int64_t n_cells, const double *state
   a.seg = reinterpret_cast<double *>(static_cast<char *>(workspace) + l.sched_bytes +
                                      l.ckpt_bytes);
   a.order = reinterpret_cast<const int32_t *>(static_cast<char *>(workspace) + l.o_order);
+  a.soff = reinterpret_cast<int64_t *>(static_cast<char *>(workspace) + l.o_soff);
+  a.states = reinterpret_cast<double *>(static_cast<char *>(workspace) + l.total);
+  a.states_cap = workspace_bytes > l.total ? (int64_t)((workspace_bytes - l.total) / 8) : 0;
   a.rtol = rtol;
   a.atol = atol;
   return a;
@@ -1382,6 +1390,11 @@ size_t burn_batch_adjoint_workspace_bytes(const bn_network *net, int64_t n_cells
                                           int32_t max_steps) {
   if (!net || n_cells < 0 || max_steps < 1) return 0;
   return adj_layout(net, n_cells, max_steps).total;
+}
+
+size_t burn_batch_adjoint_states_bytes(const bn_network *net, int64_t total_steps) {
+  if (!net || total_steps < 0) return 0;
+  return 8 * (size_t)net->n * (size_t)total_steps;
 }
 
 int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const double *state0,
@@ -1420,7 +1433,7 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
   b.atol = atol;
   b.max_steps = max_steps;
   bn::AdjArgs a = adj_args(net, n_cells, state0, rho, T0, rtol, atol, log_mult, max_steps, status,
-                           workspace);
+                           workspace, workspace_bytes);
   b.sched = a.sched;
   b.sched_stride = a.sched_stride;
   b.sched_cap = a.sched_cap;
@@ -1442,6 +1455,10 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
                                  reinterpret_cast<int32_t *>(w + l.o_order), st);
     if (e != hipSuccess)
       return fail(BN_EHIP, std::string("cell order launch failed: ") + hipGetErrorString(e));
+    // the pool places of the corrected states the replay keeps
+    e = bn::launch_adjoint_states(a, st);
+    if (e != hipSuccess)
+      return fail(BN_EHIP, std::string("state pool launch failed: ") + hipGetErrorString(e));
   }
   a.Yout = state_out;
   a.Tout = T_out;
@@ -1468,7 +1485,7 @@ int burn_batch_adjoint_backward(const bn_network *net, int64_t n_cells, const do
   if (!state0 || !rho || !T0 || !gY || !gE || !grad || !status)
     return fail(BN_EINVAL, "null array argument");
   bn::AdjArgs a = adj_args(net, n_cells, state0, rho, T0, rtol, atol, log_mult, max_steps,
-                           const_cast<int32_t *>(status), workspace);
+                           const_cast<int32_t *>(status), workspace, workspace_bytes);
   a.gY = gY;
   a.gE = gE;
   a.grad = grad;

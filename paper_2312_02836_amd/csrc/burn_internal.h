@@ -158,6 +158,10 @@ struct AdjArgs {
                                 // the segment being reversed (backward)
   const int32_t *order;         // [n_cells] cell at each position (costliest first), or
                                 // nullptr for index order
+  double *states;               // pool of corrected states (forward writes, backward reads)
+  int64_t *soff;                // [n_cells] a cell's first state in the pool (doubles), or
+                                // -1 when its states do not fit (it keeps the recompute path)
+  int64_t states_cap;           // doubles in the pool
   double rtol, atol;
 };
 size_t adjoint_sched_stride(int cap);  // doubles per cell
@@ -171,6 +175,11 @@ hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipSt
 // by the call), order receives the cell at each position.
 hipError_t launch_adjoint_order(const AdjArgs &a, float *key, int32_t *pos, unsigned *hist,
                                 int32_t *order, hipStream_t stream);
+// Places the cells' corrected states in the pool: from the recorded step
+// counts (a single workgroup scan, cells in index order), soff[c] = the
+// offset of cell c's n * steps doubles, or -1 for a cell whose states do not
+// fit in a.states_cap or whose recording failed.
+hipError_t launch_adjoint_states(const AdjArgs &a, hipStream_t stream);
 // simd_waves: 3 or 2, the register budget of the kernel instance to launch
 hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
                           hipStream_t stream);

@@ -82,6 +82,44 @@ def test_adjoint_synth21(gpu, oracle):
     _check_adjoint(gpu, oracle, cfg.networks[0], cfg.cells[0], cfg.t_end)
 
 
+@pytest.mark.parametrize("which", [(5, 0, 261), (4, 3, 33)])
+def test_adjoint_state_pool_bitwise(gpu, which):
+    """The corrected states the replay keeps in the workspace's pool are the
+    doubles the reverse sweep would recompute from checkpoints: end state,
+    E and gradients are bitwise the same with no pool, a pool for part of
+    the cells and a pool for all of them (and the pool grows to fit on a
+    second forward call).  21/60 network (two cells per wave) and 50/150
+    (one cell per wave)."""
+    import torch
+    cfg_n, item, C = which
+    cfg = synth.config(cfg_n, n_cells=C)
+    spec, cells = cfg.networks[item], cfg.cells[item]
+    gY, gE = _cot(spec, C, 3)
+    net = gpu.Network(spec)
+    outs, pools = [], []
+    for steps in (None, "half", "all", "grow"):
+        if steps in ("half", "all"):
+            total = outs[0][-1]
+            steps = total // 2 if steps == "half" else total
+        run = gpu.AdjointRun(net, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL,
+                             max_steps=2048, states_steps=None if steps == "grow" else steps)
+        if steps == "grow":
+            run.forward()
+            run.backward(gY, gE)
+        Y, T, E, st = run.forward()
+        g = run.backward(gY, gE)
+        torch.cuda.synchronize()
+        pools.append(run.pool_steps)
+        outs.append((Y.cpu().numpy(), T.cpu().numpy(), E.cpu().numpy(), st.cpu().numpy(),
+                     g.cpu().numpy(), run.recorded_steps()))
+    net.close()
+    assert pools[0] == 0 and 0 < pools[1] < pools[2] and pools[3] >= pools[2]
+    assert np.all(outs[0][3] == 0)
+    for o in outs[1:]:
+        for a, b in zip(o[:5], outs[0][:5]):
+            assert np.array_equal(a, b)
+
+
 def test_adjoint_synth13_with_multipliers(gpu, oracle):
     cfg = synth.config(2, n_cells=130)
     lm = np.random.default_rng(7).normal(0.0, 0.3, cfg.networks[0].n_reactions)
