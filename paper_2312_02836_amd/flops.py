@@ -127,17 +127,19 @@ def total_flops(spec, counters: np.ndarray) -> float:
     return float(cell_flops(spec, counters).sum())
 
 
-def adjoint_cell_flops(spec, counters: np.ndarray, replay_iters: np.ndarray) -> np.ndarray:
+def adjoint_cell_flops(spec, counters: np.ndarray, replay_iters: np.ndarray,
+                       recomputed=False) -> np.ndarray:
     """Per-cell algorithmic operation count of one sensitivity run (recording
-    burn, replay with exact correctors, checkpointed recomputation and the
-    reverse sweep), from the recording run's counters [8, C] and the replay's
-    Newton iterations and factorizations [2, C].
+    burn, replay with exact correctors and the reverse sweep), from the
+    recording run's counters [8, C] and the replay's Newton iterations and
+    factorizations [2, C].  recomputed (bool, or per cell) adds the second
+    replay of a cell whose corrected states were recomputed from checkpoints
+    for the reverse sweep (the cells the state pool did not hold).
 
       recording     cell_flops (the production burn)
-      replay        2 x (iterations x (F_rhs + F_solve) + factorizations x
-                    (F_jac + F_lu))  (the forward replay and the segment
-                    recomputation), plus per accepted step 2 x (rescale,
-                    predictor, update) = 2 x 174 n
+      replay        iterations x (F_rhs + F_solve) + factorizations x
+                    (F_jac + F_lu), plus per accepted step the rescale,
+                    predictor and update (174 n)
       reverse       per accepted step: Newton matrix and factors at the
                     corrected state (F_jac + F_lu), the transposed solve
                     (2 n^2 - n), the per-reaction contraction with J^T and
@@ -150,7 +152,8 @@ def adjoint_cell_flops(spec, counters: np.ndarray, replay_iters: np.ndarray) -> 
     n_steps = c[0]
     k = per_eval_costs(spec)
     n = spec.n
-    f_replay = it * (k["rhs"] + k["solve"]) + nf * (k["jac"] + k["lu"])
+    reps = 1 + np.asarray(recomputed, dtype=np.int64)
+    f_replay = it * (k["rhs"] + k["solve"]) + nf * (k["jac"] + k["lu"]) + n_steps * 174 * n
     f_rev = 2 * k["jac"] + k["lu"] + (2 * n * n - n) + 60 * n + 2 * spec.n_reactions * 6
-    return (cell_flops(spec, counters) + 2 * f_replay + n_steps * (2 * 174 * n + f_rev)
+    return (cell_flops(spec, counters) + reps * f_replay + n_steps * f_rev
             + k["rhs"] + k["jac"])
