@@ -10,6 +10,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -610,13 +612,48 @@ ItemLaunch item_launch(const bn_network *net, const DeviceLimits &lim, int bw_op
   return r;
 }
 
+// Side streams of a device for the launches of one multi-network call that
+// run beside the first (default priority, non-blocking), with the events
+// that fork them from and join them back to the caller's stream.  Created on
+// first use and kept for the process.
+struct SideStreams {
+  hipStream_t s[BN_MAX_ITEMS] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t done[BN_MAX_ITEMS] = {};
+  bool ok = false;
+};
+std::mutex g_side_mu;
+SideStreams g_side[64];
+
+// the side streams of device dev, or null if they cannot be made
+SideStreams *side_streams(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  SideStreams &x = g_side[dev];
+  if (x.ok) return &x;
+  bool good = hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; good && i < BN_MAX_ITEMS; ++i)
+    good = hipStreamCreateWithFlags(&x.s[i], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&x.done[i], hipEventDisableTiming) == hipSuccess;
+  if (!good) {
+    (void)hipGetLastError();
+    return nullptr;  // the launches then run in order on the caller's stream
+  }
+  x.ok = true;
+  return &x;
+}
+
 // burn_batch_multi with the workspace given (the caller's, or the library's
 // static scratch for burn_batch_multi_noalloc).  Items that run at the same
 // waves per SIMD share one persistent launch; a call with items of both
 // kinds makes two launches, so that small networks are not held to the
-// occupancy of large ones.
+// occupancy of large ones, and each generated network has a launch of its
+// own.  With several launches, all but the first go to side streams forked
+// from the caller's stream and joined back before the write-back, so that
+// one launch's tail overlaps the others (allow_fork false, or a stream under
+// graph capture: all in order on the caller's stream).
 int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rtol, double atol,
-               const bn_burn_opts *opts, void *workspace, size_t workspace_bytes, void *stream) {
+               const bn_burn_opts *opts, void *workspace, size_t workspace_bytes, void *stream,
+               bool allow_fork) {
   if (n_items < 0 || n_items > BN_MAX_ITEMS)
     return fail(BN_EINVAL, "n_items must be 0..BN_MAX_ITEMS");
   if (n_items > 0 && !items) return fail(BN_EINVAL, "null items");
@@ -732,14 +769,16 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
       staged[j] = s;
     }
   }
-  // the generated networks' launches
+  // the launches: the generated networks', then one persistent launch per
+  // class (each a closure over its arguments, enqueued below)
+  std::vector<std::function<hipError_t(hipStream_t)>> launches;
   size_t g0 = 0;
   for (; g0 < its.size() && klass(its[g0]) == 0; ++g0) {
-    e = launch_gen(its[g0].net, staged[g0], queue + g0, st);
-    if (e != hipSuccess)
-      return fail(BN_EHIP, std::string("generated kernel launch failed: ") + hipGetErrorString(e));
+    const bn_network *gnet = its[g0].net;
+    const bn::BurnArgs ga = staged[g0];
+    unsigned long long *gq = queue + g0;
+    launches.push_back([gnet, ga, gq](hipStream_t s) { return launch_gen(gnet, ga, gq, s); });
   }
-  // one persistent launch per class
   for (size_t c0 = g0; c0 < its.size();) {
     size_t c1 = c0;
     while (c1 < its.size() && klass(its[c1]) == klass(its[c0])) ++c1;
@@ -773,10 +812,42 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     // no more workgroups than there are cells to start
     const int64_t cells_per_wg = (int64_t)bw * 16;
     grid = std::max<int64_t>(1, std::min<int64_t>(grid, (total + cells_per_wg - 1) / cells_per_wg));
-    e = bn::launch_multi(m, (int)grid, W, st);
-    if (e != hipSuccess)
-      return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    launches.push_back([m, grid, W](hipStream_t s) { return bn::launch_multi(m, (int)grid, W, s); });
     c0 = c1;
+  }
+  SideStreams *side = nullptr;
+  if (allow_fork && launches.size() > 1) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+      std::lock_guard<std::mutex> lk(g_side_mu);
+      side = side_streams(dev);
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (!side) {
+    for (auto &f : launches)
+      if ((e = f(st)) != hipSuccess)
+        return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  } else {
+    // fork: the side streams wait for what the caller's stream has enqueued
+    // (counters, order and staging); join: the caller's stream waits for them
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if ((e = hipEventRecord(side->fork, st)) != hipSuccess)
+      return fail(BN_EHIP, std::string("hipEventRecord failed: ") + hipGetErrorString(e));
+    for (size_t j = 1; j < launches.size(); ++j)
+      if ((e = hipStreamWaitEvent(side->s[j - 1], side->fork, 0)) != hipSuccess)
+        return fail(BN_EHIP, std::string("hipStreamWaitEvent failed: ") + hipGetErrorString(e));
+    for (size_t j = 0; j < launches.size(); ++j) {
+      hipStream_t sj = j == 0 ? st : side->s[j - 1];
+      if ((e = launches[j](sj)) != hipSuccess)
+        return fail(BN_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    }
+    for (size_t j = 1; j < launches.size(); ++j) {
+      if ((e = hipEventRecord(side->done[j - 1], side->s[j - 1])) != hipSuccess ||
+          (e = hipStreamWaitEvent(st, side->done[j - 1], 0)) != hipSuccess)
+        return fail(BN_EHIP, std::string("stream join failed: ") + hipGetErrorString(e));
+    }
   }
   if (o.order_cells) {
     for (size_t j = 0; j < its.size(); ++j) {
@@ -796,7 +867,8 @@ int burn_batch_multi(int32_t n_items, const bn_batch_item *items, double dt, dou
                      double atol, const bn_burn_opts *opts, void *workspace,
                      size_t workspace_bytes, void *stream) {
   g_err.clear();
-  return multi_impl(n_items, items, dt, rtol, atol, opts, workspace, workspace_bytes, stream);
+  return multi_impl(n_items, items, dt, rtol, atol, opts, workspace, workspace_bytes, stream,
+                    true);
 }
 
 int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double dt,
@@ -821,7 +893,7 @@ int burn_batch_multi_noalloc(int32_t n_items, const bn_batch_item *items, double
     return fail(BN_EHIP, std::string("hipGetSymbolAddress of the static scratch failed: ") +
                              hipGetErrorString(e));
   return multi_impl(n_items, items, dt, rtol, atol, opts, scratch,
-                    (size_t)BN_NOALLOC_SCRATCH_BYTES, stream);
+                    (size_t)BN_NOALLOC_SCRATCH_BYTES, stream, false);
 }
 
 namespace {
@@ -1206,7 +1278,7 @@ int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const doubl
           if ((e = hipMemcpyAsync(Ys, state, ybytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
           if ((e = hipMemcpyAsync(Ts, T, tbytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
           if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
-          brc = multi_impl(1, &item, dt, rtol, atol, &o, ws, wsb, stream);
+          brc = multi_impl(1, &item, dt, rtol, atol, &o, ws, wsb, stream, false);
           if (brc != BN_SUCCESS) break;
           if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
           if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
