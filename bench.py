@@ -404,7 +404,11 @@ def run_adjoint(steps: int, warmup: int, n_cells: int, cpu_seconds: float) -> di
         run.forward()
         run.backward(gY, gE)
     torch.cuda.synchronize()
-    log(f"adjoint21: warmup done ({warmup} steps)")
+    # the workspace's state pool sized from the recorded steps (outside the
+    # timed region)
+    if warmup:
+        run.fit_pool()
+    log(f"adjoint21: warmup done ({warmup} steps), state pool {run.pool_steps} steps")
     ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]

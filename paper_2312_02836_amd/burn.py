@@ -394,10 +394,11 @@ class AdjointRun:
     sum_i gY_i Y_i + gE E with respect to the log-rate multipliers.  The
     workspace (schedules, checkpoints and a pool of corrected states) is
     allocated here, from torch.  The pool starts with room for
-    ``states_steps`` accepted steps (None: none) and grows at the start of a
-    forward call to the steps the previous one recorded, so that repeated
-    runs of one batch replay every cell from the pool; cells that do not
-    fit are recomputed from checkpoints (same gradients)."""
+    ``states_steps`` accepted steps (None: none); the second forward call
+    first grows it to the steps the first one recorded (``fit_pool()`` does
+    that at any time), so that repeated runs of one batch keep every cell's
+    states; cells that do not fit are recomputed from checkpoints (the same
+    gradients)."""
 
     def __init__(self, net: Network, Y0, rho, T0, dt: float, rtol: float = 1e-6,
                  atol: float = 1e-10, log_mult=None, *, max_steps: int = 2048,
@@ -441,12 +442,19 @@ class AdjointRun:
         ok = self.status == 0
         return int(self.counters[0][ok].sum().item())
 
+    def fit_pool(self) -> None:
+        """Grow the pool to the steps the last forward call recorded (a
+        device synchronisation; the next forward call starts a new
+        forward/backward pair)."""
+        need = self.recorded_steps()
+        if need > self.pool_steps:
+            self._pool(need, self.device)
+
     def forward(self):
-        if getattr(self, "_ran", False):
-            need = self.recorded_steps()
-            if need > self.pool_steps:
-                self._pool(need, self.device)
-        self._ran = True
+        n_fwd = getattr(self, "_n_fwd", 0)
+        if n_fwd == 1:
+            self.fit_pool()
+        self._n_fwd = n_fwd + 1
         rc = _lib.lib().burn_batch_adjoint_forward(
             self.net.handle, self.C, _ptr(self.Y0), _ptr(self.rho), _ptr(self.T0), self.dt,
             self.rtol, self.atol, _ptr(self.lm), self.max_steps, _ptr(self.Y), _ptr(self.T),
