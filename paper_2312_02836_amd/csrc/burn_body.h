@@ -1110,11 +1110,17 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         }
       } else {
         double *Mrow = fM + (frow ? fi : 0) * MS;
-        for (int K = 0; K < n; ++K) {
+        // The pivot at column K: the first largest |entry| in position order
+        // among the candidate rows (pos >= K), found by one reduction over
+        // the slot's lanes (key: position, then the physical row, the payload;
+        // positions of candidates are distinct, so the smallest key is the
+        // first position).  Updates pos, fsing and fdinv; returns the pivot's
+        // physical row, and the row's entry K in mk.
+        auto pivot = [&](int K, double &mk) __attribute__((always_inline)) -> int {
           double v = -2.0;
           int nan_k = 0;
           const bool cand = frow && pos >= K;
-          double mk = 0.0;
+          mk = 0.0;
           if (cand) {
             mk = Mrow[K];
             v = fabs(mk);
@@ -1123,42 +1129,76 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               v = -1.0;
             }
           }
-          // key: position, then the physical row (the payload); positions of
-          // candidates are distinct, so the smallest key is the first position
           int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
           gargmax_key<FL>(v, key);
           const int bp = key >> 8;
-          const int prow_i = key & 255;  // physical row of the pivot
           nan_k = gor<FL>(nan_k);
           if (!(v > 0.0) || nan_k) fsing = 1;
           if (frow) {
             if (pos == K) pos = bp;
             else if (pos == bp) pos = K;
           }
-          const double *P = fM + prow_i * MS;
-          const double rinv = 1.0 / P[K];
-          if (frow && pos == K) fdinv = rinv;
+          return key & 255;
+        };
+        // Two columns per pass (the elimination's arithmetic, operation by
+        // operation, is the textbook one's): column K's pivot and multipliers
+        // l1 and the update of column K + 1 alone; then column K + 1's pivot
+        // and multipliers l2, and one sweep over the trailing columns j that
+        // applies both updates, a_j - l1 P1_j, then - l2 P2_j with P2 the
+        // pivot row of K + 1 after its own column-K update (every lane forms
+        // it, P2_j - l1' P1_j with that row's multiplier l1'): the trailing
+        // entries are read and written once per two columns.
+        for (int K = 0; K < n; K += 2) {
+          double mk;
+          const double *P1 = fM + pivot(K, mk) * MS;
+          const double rinv1 = 1.0 / P1[K];
+          if (frow && pos == K) fdinv = rinv1;
+          const bool two = K + 1 < n;
+          double l1 = 0.0;
           if (frow && pos > K) {
-            const double l = mk * rinv;
-            Mrow[K] = l;
+            l1 = mk * rinv1;
+            Mrow[K] = l1;
+            if (two) Mrow[K + 1] = fma(-l1, P1[K + 1], Mrow[K + 1]);
+          }
+          wave_lds_sync();
+          if (!two) break;
+          double mk2;
+          const double *P2 = fM + pivot(K + 1, mk2) * MS;
+          const double rinv2 = 1.0 / P2[K + 1];
+          const double l1p = P2[K];  // the multiplier of column K + 1's pivot row at column K
+          if (frow && pos == K + 1) fdinv = rinv2;
+          const bool below = frow && pos > K + 1;
+          double l2 = 0.0;
+          if (below) {
+            l2 = mk2 * rinv2;
+            Mrow[K + 1] = l2;
+          }
+          if (frow && pos > K) {
             // whole chunks of ECH columns (all loads of a chunk are issued
             // before the first use, so the LDS latency is paid once per
             // chunk), then the remaining columns one by one
-            int j0 = K + 1;
+            int j0 = K + 2;
             for (; j0 + ECH <= n; j0 += ECH) {
-              double a[ECH], b[ECH];
+              double a[ECH], b[ECH], c[ECH];
 #pragma unroll
               for (int u = 0; u < ECH; ++u) {
                 a[u] = Mrow[j0 + u];
-                b[u] = P[j0 + u];
+                b[u] = P1[j0 + u];
+                c[u] = P2[j0 + u];
               }
 #pragma unroll
               for (int u = 0; u < ECH; ++u) {
-                a[u] -= l * b[u];
+                a[u] = fma(-l1, b[u], a[u]);
+                if (below) a[u] = fma(-l2, fma(-l1p, b[u], c[u]), a[u]);
                 Mrow[j0 + u] = a[u];
               }
             }
-            for (; j0 < n; ++j0) Mrow[j0] -= l * P[j0];
+            for (; j0 < n; ++j0) {
+              const double b = P1[j0];
+              double a = fma(-l1, b, Mrow[j0]);
+              if (below) a = fma(-l2, fma(-l1p, b, P2[j0]), a);
+              Mrow[j0] = a;
+            }
           }
           wave_lds_sync();
         }
