@@ -171,11 +171,11 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
                     f"cell ({gen[-1]['seconds']} s)")
     opts = _lib.BurnOpts(0, 0, args.block_waves, 0)
     # the persistent kernel's launch choice per network: from the tuning
-    # cache, or tuned on the first 16,384 cells (outside the timed region)
+    # cache, or tuned on the first 65,536 cells (outside the timed region)
     tune = []
     if not args.no_tune and not (args.lanes or args.block_waves):
         for b in batches:
-            k = min(16384, n_cells)
+            k = min(65536, n_cells)
             t0 = time.perf_counter()
             e = B.tune_cached(b["net"], b["Y0"][:, :k].contiguous(), b["rho"][:k].contiguous(),
                               b["T0"][:k].contiguous(), cfg.t_end, cfg.rtol, cfg.atol)

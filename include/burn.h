@@ -358,7 +358,9 @@ typedef struct {
  * waves per workgroup) on a sample of cells, each as an ordered
  * burn_batch_multi launch of the sample alone, and make the fastest the
  * network's persistent choice (and its time per cell the network's cost
- * estimate).  The candidates are the table-driven kernel's: a network whose
+ * estimate), unless it beats the choice derived without tuning by less than
+ * 3 % (then that one is kept: a sample's tail weighs more than a full
+ * batch's).  The candidates are the table-driven kernel's: a network whose
  * generated kernel is selected is timed with the table body and keeps its
  * selection.  The caller's arrays are only read.  Synchronizes `stream`;
  * allocates device memory; not for use under graph capture.

@@ -722,9 +722,10 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
                                : "workspace missing or smaller than burn_batch_multi_workspace_bytes");
   if (reinterpret_cast<uintptr_t>(workspace) % 8)
     return fail(BN_EINVAL, "workspace must be 8-byte aligned");
-  // Generated networks first (each its own launch), then the two-wave class,
-  // then the one-wave class; each class costliest network first (its cells
-  // then start first and the tail is made of cheap ones).
+  // Items sorted: generated networks (each its own launch, enqueued after
+  // the table-driven launches), then the two-wave class, then the one-wave
+  // class; each class costliest network first (its cells then start first
+  // and the tail is made of cheap ones).
   auto klass = [](const It &x) {
     return x.net->body == BN_BODY_GENERATED ? 0 : (x.l.W == 2 ? 1 : 2);
   };
@@ -771,13 +772,13 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
   }
   // the launches: the generated networks', then one persistent launch per
   // class (each a closure over its arguments, enqueued below)
-  std::vector<std::function<hipError_t(hipStream_t)>> launches;
+  std::vector<std::function<hipError_t(hipStream_t)>> launches, gen_launches;
   size_t g0 = 0;
   for (; g0 < its.size() && klass(its[g0]) == 0; ++g0) {
     const bn_network *gnet = its[g0].net;
     const bn::BurnArgs ga = staged[g0];
     unsigned long long *gq = queue + g0;
-    launches.push_back([gnet, ga, gq](hipStream_t s) { return launch_gen(gnet, ga, gq, s); });
+    gen_launches.push_back([gnet, ga, gq](hipStream_t s) { return launch_gen(gnet, ga, gq, s); });
   }
   for (size_t c0 = g0; c0 < its.size();) {
     size_t c1 = c0;
@@ -815,6 +816,10 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     launches.push_back([m, grid, W](hipStream_t s) { return bn::launch_multi(m, (int)grid, W, s); });
     c0 = c1;
   }
+  // the generated networks' launches after the table-driven ones: a
+  // generated workgroup takes a whole compute unit's LDS, so it fills the
+  // units the long table-driven launches free towards their end
+  for (auto &f : gen_launches) launches.push_back(std::move(f));
   SideStreams *side = nullptr;
   if (allow_fork && launches.size() > 1) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1255,6 +1260,19 @@ int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const doubl
   // given its selection back at the end
   const int saved_body = net->body;
   net->body = BN_BODY_TABLE;
+  // the choice derived without tuning (the network's plain shape, two waves
+  // per SIMD when the LDS allows): a candidate replaces it only when it is
+  // faster on the sample by more than the margin, since a sample's tail
+  // weighs more than a full batch's and one timing per candidate is noisy
+  ItemLaunch dflt{};
+  {
+    const int pw = net->pW;
+    net->pW = 0;
+    dflt = item_launch(net, lim, 0);
+    net->pW = pw;
+  }
+  constexpr double kMargin = 0.97;
+  double dflt_ms = -1.0;
   double best = -1.0;
   int best_c[4] = {0, 0, 0, 0};
   int nres = 0;
@@ -1306,6 +1324,7 @@ int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const doubl
           rc = fail(BN_EHIP, std::string("autotune launch failed: ") + hipGetErrorString(e));
           break;
         }
+        if (W == dflt.W && sh.L == dflt.L && sh.S == dflt.S && bw == dflt.bw) dflt_ms = ms;
         if (best < 0.0 || ms < best) {
           best = ms;
           best_c[0] = sh.L;
@@ -1321,6 +1340,13 @@ int bn_network_autotune_persistent(bn_network *net, int64_t n_cells, const doubl
   (void)hipStreamSynchronize(st);
   (void)hipFree(scratch);
   net->body = saved_body;
+  if (best >= 0.0 && dflt_ms >= 0.0 && !(best < kMargin * dflt_ms)) {
+    best = dflt_ms;
+    best_c[0] = dflt.L;
+    best_c[1] = dflt.S;
+    best_c[2] = dflt.W;
+    best_c[3] = dflt.bw;
+  }
   if (n_results) *n_results = std::min(nres, max_results > 0 ? max_results : 0);
   if (rc != BN_SUCCESS || best < 0.0) {
     net->pL = saved[0];

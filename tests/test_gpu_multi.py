@@ -290,7 +290,8 @@ def test_synth50_full_size_sampled(gpu, oracle):
 
 def test_persistent_autotune_cache_then_burn(gpu, oracle, tmp_path):
     """Tune the persistent kernel on a sample (cache miss: every fitting
-    shape, waves-per-SIMD class and workgroup size timed), reload the choice
+    shape, waves-per-SIMD class and workgroup size timed; the untuned choice
+    is kept unless a candidate beats it by 3 %), reload the choice
     from the cache for a fresh handle of the same network (no timing), and
     burn with it: parity with the oracle."""
     cfg = synth.config(2, n_cells=8192)
@@ -304,8 +305,12 @@ def test_persistent_autotune_cache_then_burn(gpu, oracle, tmp_path):
     assert {c[2] for c in timed} == {1, 2}  # both waves-per-SIMD classes
     choice = net.get_persistent_launch()
     assert list(choice) == e1["persistent"]
+    # the fastest candidate, unless it beats the untuned choice (then the
+    # one kept) by less than 3 %
     best = min(timed, key=lambda c: c[4])
-    assert tuple(best[:4]) == choice
+    if tuple(best[:4]) != choice:
+        kept = [c for c in timed if tuple(c[:4]) == choice]
+        assert kept and best[4] >= 0.97 * kept[0][4], (best, kept)
     net2 = gpu.Network(spec)
     e2 = gpu.tune_cached(net2, cells.Y, cells.rho, cells.T, cfg.t_end, RTOL, ATOL, cache=cache)
     assert e2["hit"] and net2.get_persistent_launch() == choice
