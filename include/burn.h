@@ -97,7 +97,15 @@ typedef struct {
 /* Validate `desc` (indices in range, every reaction conserves mass number,
  * finite coefficients, c_v > 0), build the device tables and return a handle
  * in *out.  Returns BN_SUCCESS, BN_EINVAL, BN_EUNSUPPORTED, BN_ENOMEM or
- * BN_EHIP.  The handle is bound to the device current at creation. */
+ * BN_EHIP.  The handle is bound to the device current at creation.
+ * An unscreened network of more than 16 components also gets the areas in
+ * which its persistent launches (burn_batch_multi, _noalloc) keep every
+ * cell's Jacobian between refreshes (shapes that factor in LDS): 16 n^2
+ * doubles per compute unit for n <= 32, else 8 n^2 (16 MB for n = 22, 43 MB
+ * for n = 51 on 256 units), held until bn_network_destroy; if that
+ * allocation fails the launches assemble the Jacobian at every
+ * factorization instead (same results).  Two persistent launches of such a
+ * network must not be in flight at once (they share its areas). */
 int bn_network_create(const bn_network_desc *desc, bn_network **out);
 
 /* Free the handle and its device tables (NULL is a no-op).  The caller must
@@ -203,6 +211,9 @@ size_t burn_batch_multi_order_workspace_bytes(int32_t n_items, const bn_batch_it
  *                               burn_batch_multi_order_workspace_bytes), 8-byte
  *                               aligned, caller-owned; it must not be used by
  *                               another launch in flight
+ * A network of more than 16 components keeps its cells' Jacobians between
+ * refreshes in areas of its own (bn_network_create); two launches of one
+ * such network must not be in flight at once.
  * With order_cells = 1 each network's queue hands out its cells in order of
  * increasing initial step size h0 (the integrator's first-step estimate
  * 0.01 ||y0|| / ||f(y0)||, the same weighted norms as in the burn), so the

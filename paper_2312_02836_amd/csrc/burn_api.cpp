@@ -54,6 +54,10 @@ struct bn_network {
   bn::GenDesc desc;         // host copy for code generation
   GenKernel *gen = nullptr;
   int body = BN_BODY_TABLE;
+  // per-wave Jacobian areas of the persistent launches that factor in LDS
+  // (systems above 16 components; see bn::BurnArgs::jws)
+  void *jws = nullptr;
+  size_t jws_bytes = 0;
 };
 
 namespace {
@@ -427,6 +431,24 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
   t.wsq = reinterpret_cast<const double *>(base + o_wsq);
   net->screened = d->screen != nullptr;
   fill_desc(d, &net->desc);
+  // Room for the largest persistent grid of a shape that factors in LDS:
+  // at most eight waves per compute unit, each holding 64 / L cells of
+  // n^2 doubles (16 n^2 per unit when n <= 32 admits the 32-row shapes,
+  // else 8 n^2).  Without it (allocation failed) every pass assembles J.
+  if (!net->screened && t.n > 16) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, net->device) ==
+            hipSuccess &&
+        cus > 0) {
+      const size_t jb = (size_t)cus * (t.n <= 32 ? 16 : 8) * (size_t)t.n * (size_t)t.n * 8;
+      if (hipMalloc(&net->jws, jb) == hipSuccess) {
+        net->jws_bytes = jb;
+      } else {
+        net->jws = nullptr;
+        (void)hipGetLastError();
+      }
+    }
+  }
   *out = net;
   return BN_SUCCESS;
 }
@@ -434,6 +456,7 @@ int bn_network_create(const bn_network_desc *d, bn_network **out) {
 void bn_network_destroy(bn_network *net) {
   if (!net) return;
   if (net->dev) (void)hipFree(net->dev);
+  if (net->jws) (void)hipFree(net->jws);
   free_gen(net->gen);
   delete net;
 }
@@ -813,6 +836,22 @@ int multi_impl(int32_t n_items, const bn_batch_item *items, double dt, double rt
     // no more workgroups than there are cells to start
     const int64_t cells_per_wg = (int64_t)bw * 16;
     grid = std::max<int64_t>(1, std::min<int64_t>(grid, (total + cells_per_wg - 1) / cells_per_wg));
+    // the items that factor in LDS keep J(y_J) per cell in their network's
+    // areas when those hold this grid
+    for (size_t j = c0; j < c1; ++j) {
+      const int L = its[j].l.L, S = its[j].l.S, NP = L * S;
+      bn::BurnArgs &ia = m.item[j - c0];
+      ia.jws = nullptr;
+      ia.jws_wave = 0;
+      if ((S > 1 || NP >= 32) && its[j].net->jws) {
+        const int64_t rows = NP >= 32 ? ia.net.n : NP;
+        const int64_t per_wave = (int64_t)(64 / L) * rows * rows;
+        if ((size_t)(grid * bw * per_wave) * 8 <= its[j].net->jws_bytes) {
+          ia.jws = static_cast<double *>(its[j].net->jws);
+          ia.jws_wave = per_wave;
+        }
+      }
+    }
     launches.push_back([m, grid, W](hipStream_t s) { return bn::launch_multi(m, (int)grid, W, s); });
     c0 = c1;
   }

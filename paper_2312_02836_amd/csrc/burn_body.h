@@ -431,6 +431,16 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   double *facc = wb + (size_t)CPW * DS + (size_t)CPW * YS + (size_t)cw * YS;
   double *fbase = wb + (size_t)CPW * DS + 2 * (size_t)CPW * YS;
   double *fsc = fbase + (size_t)FC * FB;
+  // this wave's Jacobian areas (shapes that factor in LDS, when the launch
+  // provides them): cell c of the wave keeps J(y_J) at jw + c MROWS^2,
+  // column-major
+  double *jw = nullptr;
+  if constexpr (!REG_LU) {
+    if (a.jws) {
+      const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+      jw = a.jws + (size_t)wv * (size_t)a.jws_wave;
+    }
+  }
 
   const double *s_rtab = tb.rtab, *s_emult = tb.emult, *s_q = tb.q, *s_qcv = tb.qcv;
   const int *s_rsp = tb.rsp, *s_rout = tb.rout;
@@ -439,7 +449,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   double LU[S][NP];  // factor rows held at positions s*L+q
   // register factorization: row q of the cell's J(y_J), kept between passes
   double Jr[REG_LU ? NP : 1];
-  int jr_ok = 0;  // Jr holds J(y_J)
+  int jr_ok = 0;  // J(y_J) is held (in Jr, or in the cell's workspace area)
   double dinv[S];    // 1 / U_pp of those rows
   int ridx[S];       // natural index of those rows
   double yp[S], psi[S], isc[S], dd[S], yv[S], yJ[S], F[S];
@@ -880,6 +890,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         if (q == 0) {
           fsc[4 * myslot + 0] = cc;
           fsc[4 * myslot + 1] = rho;
+          // the cell's area holds J(y_J) (read in (b), overwritten in (d))
+          fsc[4 * myslot + 2] = (jw && jr_ok) ? 1.0 : 0.0;
         }
       }
       wave_lds_sync();
@@ -898,20 +910,22 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       const double frho = fsel >= 0 ? fsc[4 * fj + 1] : 1.0;
       const bool frow = fi < MROWS;
       double *uacc = fM + (size_t)MROWS * MS;  // screening: sum_r W_ir h_r R_r
-      // With register factorization J(y_J) is kept in the lanes' Jr registers
-      // and assembled (into LDS, unscaled, from a zero matrix) only when it
-      // was refreshed; otherwise the pass builds I - cJ from Jr.  Without it,
-      // every pass assembles I - cJ itself from the identity.
-      bool asm_j = true;
+      // J(y_J) is assembled (into LDS, unscaled, from a zero matrix) only
+      // when it was refreshed: with register factorization it is kept in the
+      // lanes' Jr registers, otherwise in the cell's area of the workspace
+      // (without one, every pass assembles it); the pass then builds I - cJ
+      // from it.
+      bool asm_j;
       if constexpr (REG_LU) asm_j = fsel >= 0 && !jr_ok;
-      const bool any_asm = !REG_LU || __ballot(asm_j) != 0;
+      else asm_j = fsel >= 0 && !(fsc[4 * fj + 2] != 0.0);
+      const bool any_asm = __ballot(asm_j) != 0;
       int jbad = 0;
       if (any_asm) {
       if constexpr (SH::COMPACT) {
         if (frow) {
           if constexpr (SCR) uacc[fi] = 0.0;
           double *mr = fM + fi * MS;
-          for (int j = 0; j < MROWS; ++j) mr[j] = (fi == j) ? 1.0 : 0.0;
+          for (int j = 0; j < MROWS; ++j) mr[j] = 0.0;
         }
       } else {
         // the slot's FL lanes zero its matrix together (consecutive
@@ -920,14 +934,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         for (int i = 0; i < NP * (NP + 1); i += FL) fM[i + fi] = 0.0;
         wave_lds_sync();
         if constexpr (SCR) uacc[fi] = 0.0;
-        if constexpr (!REG_LU) fM[fi * MS + fi] = 1.0;
       }
       wave_lds_sync();
-      // the scale of the assembled terms: -c into I - cJ, or 1 into J
-      const double ascale = REG_LU ? 1.0 : -fcc;
       // Rates at y_J for the reactions r = fi, fi+FL, ...; every Jacobian term
       // W(i, r) dR_r/dy_j (W = nu for a species row, q/c_v for the temperature
-      // row) is added, times -c, into the Newton matrix I - cJ.
+      // row) is added into J.
       double fG = 0.0, fS = 1.0;
       if (fsel >= 0 && asm_j) {
         const double T = fy[N];
@@ -988,7 +999,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
             const int col = (aa < 3) ? sp[aa] : N;
             if (col >= 0) {
               if (!isfinite(g[aa])) jbad = 1;
-              const double val = ascale * g[aa];
+              const double val = g[aa];
               Unroll<6>::run([&]<int E>() __attribute__((always_inline)) {
                 if (E < ne) {
                   const Ent en = ent_of<E>(r0, r1);
@@ -1019,7 +1030,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         // rank-one composition term: -c u_i dG/dY_j, dG/dY_j = G A_j^2 / (2 S)
         wave_lds_sync();
         if (fsel >= 0 && asm_j && fi < n) {
-          const double ui = ascale * uacc[fi] * fG / (2.0 * fS);
+          const double ui = uacc[fi] * fG / (2.0 * fS);
           double *mr = fM + fi * MS;
           for (int j = 0; j < N; ++j) mr[j] += ui * nt.wsq[j];
           if (!isfinite(ui)) jbad = 1;
@@ -1028,6 +1039,33 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
       }  // any_asm
       jbad = gor<FL>(jbad);
       wave_lds_sync();
+      if constexpr (!REG_LU) {
+        // I - cJ, row by row, from the J just assembled (copied to the
+        // cell's area when there is one) or from the one kept there, whose
+        // loads go out eight at a time
+        if (fsel >= 0 && frow) {
+          double *mr = fM + fi * MS;
+          const int jo = fsel * MROWS * MROWS + fi;  // the row's first entry in the area
+          if (asm_j) {
+            for (int j = 0; j < MROWS; ++j) {
+              const double v = mr[j];
+              if (jw) jw[jo + j * MROWS] = v;
+              mr[j] = (fi == j ? 1.0 : 0.0) - fcc * v;
+            }
+          } else {
+            for (int j0 = 0; j0 < MROWS; j0 += 8) {
+              double v[8];
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+                v[u] = j0 + u < MROWS ? jw[jo + (j0 + u) * MROWS] : 0.0;
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+                if (j0 + u < MROWS) mr[j0 + u] = (fi == j0 + u ? 1.0 : 0.0) - fcc * v[u];
+            }
+          }
+        }
+        wave_lds_sync();
+      }
       // (c) LU with partial pivoting, one row per lane.  Rows are not moved:
       // `pos` is the position the row would hold after the textbook row swaps
       // (the first largest |pivot| in position order wins).
@@ -1249,6 +1287,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           lu_ok = 1;
         }
         first_jac = 0;
+        // the cell's area now holds J(y_J)
+        if constexpr (!REG_LU) jr_ok = jw ? 1 : 0;
       }
       wave_lds_sync();
     }

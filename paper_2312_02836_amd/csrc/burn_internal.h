@@ -66,6 +66,13 @@ struct BurnArgs {
   // a workgroup takes positions from the part of its XCD and, when that is
   // exhausted, from the others.  nullptr: one counter (MultiArgs::queue).
   unsigned long long *parts;
+  // Shapes that factor in LDS (not in registers): per wave of the launch
+  // grid an area of jws_wave doubles, one rows x rows block per cell of the
+  // wave (column-major), that keeps the cell's J(y_J) from its assembly
+  // until the Jacobian is refreshed; the passes between form I - cJ from it
+  // instead of assembling J again.  nullptr: every pass assembles J.
+  double *jws;
+  int64_t jws_wave;
 };
 constexpr int XCD_PARTS = 8;  // MI355X: workgroup b runs on XCD b % 8
 
