@@ -484,7 +484,9 @@ adjoint_kernel(AdjArgs a) {
       }
       const bool do_fac = !done && fresh;
       if (do_fac) ++n_lu;
-      const int nonsing = factor(do_fac);
+      // (a factorization pass in which no cell of the wave factors changes
+      // nothing, so the wave skips it)
+      const int nonsing = __ballot(do_fac) != 0 ? factor(do_fac) : 1;
       if (do_fac && !nonsing) {
         ok = 0;
         done = true;
