@@ -43,6 +43,12 @@
 namespace bn {
 namespace {
 
+// pointers into device global memory (address space 1): the accesses through
+// them are global, not flat, instructions
+typedef __attribute__((address_space(1))) double *gdptr;
+typedef const __attribute__((address_space(1))) double *gcdptr;
+typedef __attribute__((address_space(1))) int32_t *giptr;
+
 constexpr double kSafety = 0.9;
 constexpr double kMinFactor = 0.2;
 constexpr double kMaxFactor = 10.0;
@@ -419,9 +425,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   // registers together, and a spill of it reloads all of them.
   int64_t C = a.n_cells;
   double rtol = a.rtol, atol = a.atol, t_end = a.t_end;
-  double *gY = a.Y, *gT = a.T;
-  const double *grho = a.rho;
-  int32_t *gst = a.status, *gcnt = a.counters;
+  // (global, not flat, pointers: a flat access also counts as an LDS
+  // access, so an LDS wait after a flat store would wait for the store)
+  gdptr gY = (gdptr)a.Y, gT = (gdptr)a.T;
+  gcdptr grho = (gcdptr)a.rho;
+  giptr gst = (giptr)a.status, gcnt = (giptr)a.counters;
   int max_steps = a.max_steps;
   asm volatile("" : "+s"(C), "+s"(rtol), "+s"(atol), "+s"(t_end));
   asm volatile("" : "+s"(gY), "+s"(gT), "+s"(grho), "+s"(gst), "+s"(gcnt), "+s"(max_steps));
@@ -434,11 +442,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   // this wave's Jacobian areas (shapes that factor in LDS, when the launch
   // provides them): cell c of the wave keeps J(y_J) at jw + c MROWS^2,
   // column-major
-  double *jw = nullptr;
+  gdptr jw = nullptr;
   if constexpr (!REG_LU) {
     if (a.jws) {
       const int wv = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-      jw = a.jws + (size_t)wv * (size_t)a.jws_wave;
+      jw = (gdptr)a.jws + (size_t)wv * (size_t)a.jws_wave;
     }
   }
 

@@ -146,6 +146,8 @@ __device__ __forceinline__ int dpp_i32(int v) {
 // a pointer into device global memory (address space 1), so the accesses
 // through it are global (not flat) instructions
 typedef __attribute__((address_space(1))) double *gptr;
+typedef const __attribute__((address_space(1))) double *gcptr;
+typedef __attribute__((address_space(1))) int *giptr;
 
 constexpr int QP_XOR1 = 0xB1;  // [1,0,3,2]
 constexpr int QP_EVEN = 0xA0;  // [0,0,2,2]
@@ -209,9 +211,11 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
   // launch constants, each kept in scalar registers of its own
   long long C = a.n_cells;
   double rtol = a.rtol, atol = a.atol, t_end = a.t_end;
-  double *gY = a.Y, *gT = a.T;
-  const double *grho = a.rho;
-  int *gst = a.status, *gcnt = a.counters;
+  // (global, not flat, pointers: a flat access also counts as an LDS
+  // access, so an LDS wait after a flat store would wait for the store)
+  gptr gY = (gptr)a.Y, gT = (gptr)a.T;
+  gcptr grho = (gcptr)a.rho;
+  giptr gst = (giptr)a.status, gcnt = (giptr)a.counters;
   int max_steps = a.max_steps;
   asm volatile("" : "+s"(C), "+s"(rtol), "+s"(atol), "+s"(t_end));
   asm volatile("" : "+s"(gY), "+s"(gT), "+s"(grho), "+s"(gst), "+s"(gcnt), "+s"(max_steps));
