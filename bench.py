@@ -185,6 +185,14 @@ def run_burn(wl_name: str, steps: int, warmup: int, args, compare: bool, cpu_sec
                          "seconds": round(time.perf_counter() - t0, 2)})
             log(f"{wl_name}: persistent choice {e['persistent']} "
                 f"({'cache' if e['hit'] else 'tuned'})")
+            if wl["mode"] == "plain":
+                # the plain launch shape too (timed on the same sample)
+                t0 = time.perf_counter()
+                B.autotune(b["net"], b["Y0"][:, :k].contiguous(), b["rho"][:k].contiguous(),
+                           b["T0"][:k].contiguous(), cfg.t_end, cfg.rtol, cfg.atol)
+                tune[-1]["plain_choice"] = list(b["net"].get_launch())
+                tune[-1]["plain_seconds"] = round(time.perf_counter() - t0, 2)
+                log(f"{wl_name}: plain choice {tune[-1]['plain_choice']}")
 
     def restore():
         for b in batches:

@@ -331,7 +331,9 @@ typedef struct {
 /* Time every launch shape that fits this network on a sample of cells (the
  * caller's arrays are only read: the sample is burned in library-allocated
  * scratch copies) and make the fastest the network's launch choice, used by
- * burn_batch (lanes_per_cell = 0) and burn_batch_multi.  Synchronizes
+ * burn_batch (lanes_per_cell = 0) and burn_batch_multi.  Each shape runs
+ * once to warm up, then is timed once, or three times (the fastest counts)
+ * when a run takes under 10 ms.  Synchronizes
  * `stream`; allocates device memory; not for use under graph capture.
  *   state, rho, T  DEVICE sample in the burn_batch layout (n_cells >= 1)
  *   results        HOST [max_results] or NULL; *n_results = entries written

@@ -1194,7 +1194,11 @@ int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
       a.max_steps = max_steps > 0 ? max_steps : 100000;
       double ms = 0.0;
       hipError_t e = hipSuccess;
-      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // first run warms up
+      // the first run warms up; then the fastest of one timed run, or of
+      // three when runs are short (a few milliseconds, where one run's
+      // noise is comparable to the differences between shapes)
+      int runs = 2;
+      for (int rep = 0; rep < runs && e == hipSuccess; ++rep) {
         if ((e = hipMemcpyAsync(Ys, state, ybytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
         if ((e = hipMemcpyAsync(Ts, T, tbytes, hipMemcpyDeviceToDevice, st)) != hipSuccess) break;
         if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
@@ -1203,7 +1207,12 @@ int bn_network_autotune(bn_network *net, int64_t n_cells, const double *state,
         if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
         float f = 0.0f;
         if ((e = hipEventElapsedTime(&f, e0, e1)) != hipSuccess) break;
-        ms = f;
+        if (rep == 1) {
+          ms = f;
+          if (f < 10.0f) runs = 4;
+        } else if (rep > 1 && f < ms) {
+          ms = f;
+        }
       }
       if (results && nres < max_results) {
         results[nres].lanes_per_cell = L;
