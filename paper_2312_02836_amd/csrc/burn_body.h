@@ -624,8 +624,12 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     // are padding (zero right-hand side, zero factor columns, unit
     // diagonal): with all NP rows stored they change nothing, so only the
     // compact layout skips them.
+    // (n is made opaque before each sweep, so the column tests are not kept
+    // from one sweep to the other)
+    int nf = n;
+    asm volatile("" : "+s"(nf));
     Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
-      if (!SH::COMPACT || K < n) {
+      if (!SH::COMPACT || K < nf) {
         const double xk = gbcast<L, K % L>(b[K / L]);
         // the factor column masked to the strictly lower part (a select
         // that does not wait for xk) and an unconditional update: b - 0 xk
@@ -640,9 +644,11 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     // back substitution with the upper factor: at step K component K is
     // final, x_K = b_K / U_KK goes to the components above it; each lane
     // scales its own components once at the end (the same product)
+    int nb = n;
+    asm volatile("" : "+s"(nb));
     Unroll<NP>::run([&]<int KK>() __attribute__((always_inline)) {
       constexpr int K = NP - 1 - KK;
-      if (!SH::COMPACT || K < n) {
+      if (!SH::COMPACT || K < nb) {
         const double xk = gbcast<L, K % L>(b[K / L] * dinv[K / L]);
 #pragma unroll
         for (int s = 0; s <= K / L; ++s) {
