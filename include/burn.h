@@ -422,7 +422,9 @@ int bn_network_get_persistent_launch(const bn_network *net, int32_t *lanes_per_c
  * one 16-step segment for the reverse sweep, and the order in which the
  * replay and the reverse sweep take the cells (most recorded steps first,
  * so that the cells sharing a wave have similar step counts; 12 bytes per
- * cell, and 8 bytes per cell for the pool offsets); the forward call fills
+ * cell, and 8 bytes per cell for the pool offsets), and the recording run's
+ * queue counter (the recording run takes cells from a device queue on a
+ * grid sized to the GPU, as burn_batch_multi does); the forward call fills
  * it, the backward call reads it (same net, cells, dt, tolerances, log_mult,
  * max_steps and workspace_bytes), and it must not be shared by calls in
  * flight.  Bytes beyond that minimum are the pool of corrected states: the

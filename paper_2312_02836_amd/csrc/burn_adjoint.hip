@@ -47,21 +47,21 @@ constexpr double ADJ_TOL = 1e-10;
 constexpr int GR = 4;           // reactions per lane in the gradient (R <= 256)
 
 // ---------------------------------------------------------------------------
-// Recording run: the plain kernel with the schedule recorder.
+// Recording run: the burn with the schedule recorder.
 
+// The recording run on a persistent grid: lane groups take the next cell
+// from a device queue counter (zeroed before the launch) as theirs finish.
 template <int L, int S, int W>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
-burn_record_kernel(BurnArgs a, int block_waves) {
+burn_record_queue_kernel(BurnArgs a, unsigned long long *queue) {
   using SH = Shape<L, S>;
   extern __shared__ double smem[];
   load_tables(a.net, a.log_mult, smem);
   __syncthreads();
   const Tabs tb = tabs_at(smem, a.net.R);
   const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
   double *wb = smem + tab_doubles_of(a.net.R) + (size_t)wave * SH::wave_doubles(a.net.n);
-  const int64_t first = ((int64_t)blockIdx.x * block_waves + wave) * SH::CPW + lane / L;
-  run_cells<L, S, false, true>(a, tb, wb, first, nullptr);
+  run_cells<L, S, true, true>(a, tb, wb, 0, queue);
 }
 
 // ---------------------------------------------------------------------------
@@ -785,24 +785,23 @@ size_t adjoint_lds_bytes(int R, int n, int waves) {
 }
 int adjoint_cells_per_wave(int n) { return 64 / adj_group(n); }
 
-hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream) {
-#define BN_REC(l, s, w)                                                                          \
+hipError_t launch_record_queue(const BurnArgs &a, int L, int S, int block_waves, int grid,
+                               unsigned long long *queue, hipStream_t stream) {
+#define BN_RECQ(l, s, w)                                                                         \
   if (L == l && S == s) {                                                                      \
     using SH = Shape<l, s>;                                                                    \
     const size_t lds =                                                                         \
         8 * (tab_doubles_of(a.net.R) + (size_t)block_waves * SH::wave_doubles(a.net.n));       \
-    const int64_t per = (int64_t)SH::CPW * block_waves;                                        \
-    const int64_t blocks = (a.n_cells + per - 1) / per;                                        \
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;                                      \
-    hipLaunchKernelGGL((burn_record_kernel<l, s, w>), dim3((unsigned)blocks),                  \
-                       dim3(64 * block_waves), lds, stream, a, block_waves);                   \
+    hipLaunchKernelGGL((burn_record_queue_kernel<l, s, w>), dim3((unsigned)grid),              \
+                       dim3(64 * block_waves), lds, stream, a, queue);                         \
     return hipGetLastError();                                                                  \
   }
-  BN_REC(8, 1, 2)
-  BN_REC(16, 1, 2)
-  BN_REC(32, 1, 2)
-  BN_REC(64, 1, 1)
-#undef BN_REC
+  if (grid < 1) return hipErrorInvalidValue;
+  BN_RECQ(8, 1, 2)
+  BN_RECQ(16, 1, 2)
+  BN_RECQ(32, 1, 2)
+  BN_RECQ(64, 1, 1)
+#undef BN_RECQ
   return hipErrorInvalidValue;
 }
 

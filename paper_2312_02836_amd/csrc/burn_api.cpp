@@ -1423,6 +1423,7 @@ struct AdjLayout {
   size_t sched_bytes, ckpt_bytes, seg_bytes;
   size_t o_key, o_pos, o_order, o_hist;  // the cell order (costliest first)
   size_t o_soff;                         // per cell, its states' offset in the pool
+  size_t o_queue;                        // the recording run's queue counter
   size_t total;                          // the minimum; a pool of states may follow
 };
 
@@ -1448,6 +1449,8 @@ AdjLayout adj_layout(const bn_network *net, int64_t n_cells, int cap) {
   o += align256(8 * (size_t)bn::ORDER_BUCKETS);
   l.o_soff = o;
   o += align256(8 * (size_t)n_cells);
+  l.o_queue = o;
+  o += align256(8);
   l.total = o;
   return l;
 }
@@ -1589,7 +1592,29 @@ int burn_batch_adjoint_forward(const bn_network *net, int64_t n_cells, const dou
   while (bw > 1 && lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block) --bw;
   if (lds_bytes(net->R, L, S, net->n, bw) > lim.lds_block)
     return fail(BN_EUNSUPPORTED, "network tables and working area exceed the LDS of a workgroup");
-  hipError_t e = bn::launch_record(b, L, S, bw, st);
+  // the recording run on a persistent grid with a cell queue (cells of
+  // uneven length then share the lanes), the grid sized to the GPU as for
+  // burn_batch_multi
+  const size_t rlds = lds_bytes(net->R, L, S, net->n, bw);
+  const int W = plain_waves(L, S);
+  int per_cu = std::max(1, 4 * W / bw);
+  per_cu = std::min<int>(per_cu, (int)std::max<size_t>(1, lim.lds_cu / rlds));
+  const int64_t cells_per_wg = (int64_t)bw * (64 / L);
+  const int64_t rgrid = std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)lim.cus * per_cu, (n_cells + cells_per_wg - 1) / cells_per_wg));
+  // shapes that factor in LDS keep J(y_J) per cell in the network's areas
+  if ((S > 1 || L * S >= 32) && net->jws) {
+    const int64_t rows = L * S >= 32 ? net->n : L * S;
+    const int64_t per_wave = (int64_t)(64 / L) * rows * rows;
+    if ((size_t)(rgrid * bw * per_wave) * 8 <= net->jws_bytes) {
+      b.jws = static_cast<double *>(net->jws);
+      b.jws_wave = per_wave;
+    }
+  }
+  unsigned long long *rq = reinterpret_cast<unsigned long long *>(
+      static_cast<char *>(workspace) + adj_layout(net, n_cells, max_steps).o_queue);
+  hipError_t e = bn::launch_zero(rq, 1, st);
+  if (e == hipSuccess) e = bn::launch_record_queue(b, L, S, bw, (int)rgrid, rq, st);
   if (e != hipSuccess) return fail(BN_EHIP, std::string("recording launch failed: ") + hipGetErrorString(e));
   {
     // replay and reverse sweep take the cells most recorded steps first

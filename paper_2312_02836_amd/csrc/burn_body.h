@@ -1041,7 +1041,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         }
       }
       if constexpr (SCR) {
-        // rank-one composition term: -c u_i dG/dY_j, dG/dY_j = G A_j^2 / (2 S)
+        // rank-one composition term of J: u_i dG/dY_j, dG/dY_j = G A_j^2 / (2 S)
         wave_lds_sync();
         if (fsel >= 0 && asm_j && fi < n) {
           const double ui = uacc[fi] * fG / (2.0 * fS);

@@ -176,7 +176,10 @@ int adjoint_n_ckpt(int cap);
 size_t adjoint_seg_doubles(int n);    // per cell
 size_t adjoint_lds_bytes(int R, int n, int waves);
 int adjoint_cells_per_wave(int n);
-hipError_t launch_record(const BurnArgs &a, int L, int S, int block_waves, hipStream_t stream);
+// The recording run on a persistent grid of `grid` workgroups taking cells
+// from *queue (one zeroed counter).
+hipError_t launch_record_queue(const BurnArgs &a, int L, int S, int block_waves, int grid,
+                               unsigned long long *queue, hipStream_t stream);
 // Order of the cells for the replay and reverse sweep, from the recorded
 // step counts (most steps first): key, pos and hist are scratch (hist zeroed
 // by the call), order receives the cell at each position.
