@@ -33,9 +33,10 @@ struct GenKernel {
   unsigned long long *queue = nullptr;  // the unordered launch's counter
   // factorization batching of the wave (see the kernel's pass): a pass runs
   // once lu_batch cells want one or a cell has waited lu_wait iterations
-  // (12 and 3 measured best on the 13/30 launch, 19.4 ms against 22.1 ms
-  // for a pass whenever any cell wants one; results are bitwise the same)
-  int lu_batch = 12, lu_wait = 3;
+  // (12 and 7 measured best on the 13/30 launch, about 18.1 ms against
+  // 22.1 ms for a pass whenever any cell wants one; results are bitwise the
+  // same)
+  int lu_batch = 12, lu_wait = 7;
 };
 
 struct bn_network {
