@@ -176,8 +176,10 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
 // BACKWARD = false: replay from y(0), write the checkpoints, the end state
 // and E.  BACKWARD = true: reverse sweep.  W is the waves per SIMD the
 // registers are budgeted for (3 when the LDS lets three waves per SIMD
-// reside, else 2); G the lanes per cell.
-template <bool BACKWARD, int W, int G>
+// reside, else 2); G the lanes per cell.  POOL (reverse sweep): the
+// instance for the cells whose corrected states are in the pool, without
+// the segment recomputation (its registers alone; the other cells rest).
+template <bool BACKWARD, int W, int G, bool POOL = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, W)))
 adjoint_kernel(AdjArgs a) {
   constexpr int CPW = 64 / G;   // cells per wave
@@ -233,10 +235,12 @@ adjoint_kernel(AdjArgs a) {
     ybuf[i] = 1.0;
   }
 
+  // a cell of the other part of a split reverse sweep rests here
+  const bool skip = BACKWARD && ((a.part == 1 && !has_states) || (a.part == 2 && has_states));
   // a failed recording run (or, backward, a failed replay): no replay
   const int st_in = a.status[cell];
-  const bool dead = !valid || n_rec < 0 || st_in != ST_OK;
-  if (dead && valid) {
+  const bool dead = !valid || n_rec < 0 || st_in != ST_OK || skip;
+  if (dead && valid && !skip) {
     if constexpr (BACKWARD) {
       for (int r = i; r < R; r += G) a.grad[(int64_t)r * C + cell] = 0.0;
     } else {
@@ -245,6 +249,10 @@ adjoint_kernel(AdjArgs a) {
         if (a.iters) a.iters[cell] = a.iters[C + cell] = 0;
       }
     }
+  }
+  // a reverse-sweep wave with no live cell has nothing more to write
+  if constexpr (BACKWARD) {
+    if (__ballot(!dead) == 0) return;
   }
   const int nst = dead ? 0 : n_rec;  // this cell's accepted steps
 
@@ -624,12 +632,14 @@ adjoint_kernel(AdjArgs a) {
 #pragma unroll
         for (int j = 0; j < DROWS; ++j) D[j] = cp[j * n + i];
       }
-      for (int mm = 0; mm < CK; ++mm) {
-        const bool act = m0 + mm < m1 && !has_states;
-        if (__ballot(act) == 0) break;  // later steps of the segment: no cell has them
-        double y_new;
-        replay_step(m0 + mm, act, y_new);
-        if (act && own) segg[mm * n + i] = y_new;
+      if constexpr (!POOL) {
+        for (int mm = 0; mm < CK; ++mm) {
+          const bool act = m0 + mm < m1 && !has_states;
+          if (__ballot(act) == 0) break;  // later steps of the segment: no cell has them
+          double y_new;
+          replay_step(m0 + mm, act, y_new);
+          if (act && own) segg[mm * n + i] = y_new;
+        }
       }
       // walk it backwards
       for (int mm = CK - 1; mm >= 0; --mm) {
@@ -826,31 +836,52 @@ hipError_t launch_adjoint_states(const AdjArgs &a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const AdjArgs &a, bool backward, int waves, int simd_waves,
+hipError_t launch_adjoint(const AdjArgs &a0, bool backward, int waves, int simd_waves,
                           hipStream_t stream) {
-  const size_t lds = adjoint_lds_bytes(a.net.R, a.net.n, waves);
-  const int G = adj_group(a.net.n);
+  const size_t lds = adjoint_lds_bytes(a0.net.R, a0.net.n, waves);
+  const int G = adj_group(a0.net.n);
   const int64_t per_block = (int64_t)waves * (64 / G);
-  const int64_t blocks = (a.n_cells + per_block - 1) / per_block;
+  const int64_t blocks = (a0.n_cells + per_block - 1) / per_block;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks), block(64 * waves);
-#define BN_ADJ(bwd, w, g) hipLaunchKernelGGL((adjoint_kernel<bwd, w, g>), grid, block, lds, stream, a)
+  const bool w3 = simd_waves >= 3;
+  AdjArgs a = a0;
+#define BN_ADJ(bwd, w, g, pool) \
+  hipLaunchKernelGGL((adjoint_kernel<bwd, w, g, pool>), grid, block, lds, stream, a)
+  if (!backward) {
+    a.part = 0;
+    if (G == 32) {
+      if (w3) BN_ADJ(false, 3, 32, false);
+      else BN_ADJ(false, 2, 32, false);
+    } else {
+      if (w3) BN_ADJ(false, 3, 64, false);
+      else BN_ADJ(false, 2, 64, false);
+    }
+    return hipGetLastError();
+  }
+  // Reverse sweep: with a pool, the cells whose states it holds run in the
+  // instance without the segment recomputation (fewer registers, no spills
+  // at three waves per SIMD), then the others in the full instance.
+  const bool split = a0.states != nullptr && a0.soff != nullptr && a0.states_cap > 0;
+  if (split) {
+    a.part = 1;
+    if (G == 32) {
+      if (w3) BN_ADJ(true, 3, 32, true);
+      else BN_ADJ(true, 2, 32, true);
+    } else {
+      if (w3) BN_ADJ(true, 3, 64, true);
+      else BN_ADJ(true, 2, 64, true);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  a.part = split ? 2 : 0;
   if (G == 32) {
-    if (backward) {
-      if (simd_waves >= 3) BN_ADJ(true, 3, 32);
-      else BN_ADJ(true, 2, 32);
-    } else {
-      if (simd_waves >= 3) BN_ADJ(false, 3, 32);
-      else BN_ADJ(false, 2, 32);
-    }
+    if (w3) BN_ADJ(true, 3, 32, false);
+    else BN_ADJ(true, 2, 32, false);
   } else {
-    if (backward) {
-      if (simd_waves >= 3) BN_ADJ(true, 3, 64);
-      else BN_ADJ(true, 2, 64);
-    } else {
-      if (simd_waves >= 3) BN_ADJ(false, 3, 64);
-      else BN_ADJ(false, 2, 64);
-    }
+    if (w3) BN_ADJ(true, 3, 64, false);
+    else BN_ADJ(true, 2, 64, false);
   }
 #undef BN_ADJ
   return hipGetLastError();

@@ -170,6 +170,8 @@ struct AdjArgs {
                                 // -1 when its states do not fit (it keeps the recompute path)
   int64_t states_cap;           // doubles in the pool
   double rtol, atol;
+  int part;                     // backward: 0 every cell, 1 the cells whose states are in
+                                // the pool, 2 the others (set by launch_adjoint)
 };
 size_t adjoint_sched_stride(int cap);  // doubles per cell
 int adjoint_n_ckpt(int cap);
