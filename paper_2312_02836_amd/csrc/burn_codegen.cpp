@@ -383,9 +383,10 @@ size_t gen_lds_bytes(const GenDesc &d, int lpc) {
   // lanes of a cell split the rates, then four waves of [rows][NS][64]: the
   // history (7 rows), psi and the reciprocal scales, and the Newton
   // correction and reciprocal pivots when they fit in the LDS of a compute
-  // unit.  The generated source carries this size and the kernel checks at
-  // compile time that its own layout needs exactly this much.
-  const size_t head = (size_t)(d.R + 7) / 8 * 8 + (lpc > 1 ? (size_t)(d.R + lpc - 1) / lpc * lpc * 8 : 0);
+  // unit; the head ends with the reciprocals 1/j of j = 0..7.  The generated
+  // source carries this size and the kernel checks at compile time that its
+  // own layout needs exactly this much.
+  const size_t head = (size_t)(d.R + 7) / 8 * 8 + (lpc > 1 ? (size_t)(d.R + lpc - 1) / lpc * lpc * 8 : 0) + 8;
   const size_t full = 8 * (head + (size_t)4 * 11 * NS * 64);
   return full <= 160 * 1024 ? full : 8 * (head + (size_t)4 * 9 * NS * 64);
 }

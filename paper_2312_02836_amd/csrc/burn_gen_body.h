@@ -61,9 +61,11 @@ constexpr int LDS_BYTES = 160 * 1024;
 
 // Doubles at the head of the LDS: the rate multipliers (R rounded up to 8),
 // then, when the LPC lanes of a cell split the rate exponentials, the rate
-// coefficient table (8 per reaction, reactions padded to a multiple of LPC).
+// coefficient table (8 per reaction, reactions padded to a multiple of LPC),
+// then the reciprocals 1/j of j = 0..7 (RECIP doubles; entry 0 unused).
+constexpr int RECIP = 8;
 constexpr int head_doubles(int R, int LPC) {
-  return (R + 7) / 8 * 8 + (LPC > 1 ? (R + LPC - 1) / LPC * LPC * 8 : 0);
+  return (R + 7) / 8 * 8 + (LPC > 1 ? (R + LPC - 1) / LPC * LPC * 8 : 0) + RECIP;
 }
 // rows per slot in LDS for a system with NS slots and R reactions: the
 // Newton correction and the reciprocal pivots go there too when four waves
@@ -202,6 +204,9 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
   constexpr int n = NET::n, N = NET::N;
   constexpr int NS = (n + LPC - 1) / LPC;
   using G = Grp<LPC>;
+  // the reciprocals 1/j at the end of the LDS head (the order-dependent
+  // quotients of the controller read them instead of dividing)
+  const double *recip = em + head_doubles(NET::R, LPC) - RECIP;
 
   const int lane = threadIdx.x & 63;
   int h = LPC == 2 ? (lane & 1) : 0;  // made opaque in every iteration (see below)
@@ -966,7 +971,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
         } else if (converged) {
           // error test, scale atol + rtol * max(|y_n|, |y_new|)
           double e1[NS], isc[NS];
-          const double rk1 = 1.0 / (double)(k + 1);
+          const double rk1 = recip[k + 1];
 #pragma unroll
           for (int s = 0; s < NS; ++s) {
             const double aa = fabs(Dref(0, s)), bb = fabs(yv[s]);
@@ -978,7 +983,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
           // exactly when ms exceeds 1 + 2^-52), and log err as (log ms) / 2
           const double ms = wms(e1, isc);
           if (ms > 0x1.0000000000001p+0) {
-            double fct = kSafety * exp(0.5 * bn::bn_log(ms) * (-1.0 / (double)(k + 1)));
+            double fct = kSafety * exp(0.5 * bn::bn_log(ms) * -rk1);
             if (fct < kMinFactor) fct = kMinFactor;
             hs *= fct;
             pend = fct;
@@ -990,7 +995,7 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
             // accept: D_{k+2} = d - D_{k+1}, D_{k+1} = d, D_j += D_{j+1}
             t = t_new;
             double em_acc = 0.0, ep_acc = 0.0;
-            const double rk = 1.0 / (double)k, rk2 = 1.0 / (double)(k + 2);
+            const double rk = recip[k], rk2 = recip[k + 2];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
               double dr[KMAX + 1];
@@ -1027,9 +1032,9 @@ __device__ __forceinline__ void run_cells(const GenArgs &a, const double *em, do
               // the factors norm^(-1/(order+1)) of orders k-1, k, k+1,
               // compared by their logarithms (log norm = (log ms) / 2); one
               // exponential for the best
-              const double lm = 0.5 * bn::bn_log(em_s) * (-1.0 / (double)k);
-              const double l0 = 0.5 * bn::bn_log(ms) * (-1.0 / (double)(k + 1));
-              const double lp = 0.5 * bn::bn_log(ep_s) * (-1.0 / (double)(k + 2));
+              const double lm = 0.5 * bn::bn_log(em_s) * -rk;
+              const double l0 = 0.5 * bn::bn_log(ms) * -rk1;
+              const double lp = 0.5 * bn::bn_log(ep_s) * -rk2;
               double best = l0;
               int dk = 0;
               if (lm > best) {
@@ -1102,8 +1107,10 @@ __device__ __forceinline__ void burn_kernel_body(const GenArgs &a) {
   for (int r = threadIdx.x; r < RB; r += blockDim.x)
     smem[r] = r < NET::R ? (a.log_mult ? exp(a.log_mult[r]) : 1.0) : 1.0;
   if constexpr (LPC > 1) {
-    for (int i = threadIdx.x; i < HEAD - RB; i += blockDim.x) smem[RB + i] = NET::ctab[i];
+    for (int i = threadIdx.x; i < HEAD - RECIP - RB; i += blockDim.x) smem[RB + i] = NET::ctab[i];
   }
+  // 1/j, correctly rounded (IEEE division)
+  if (threadIdx.x < RECIP) smem[HEAD - RECIP + threadIdx.x] = threadIdx.x ? 1.0 / (double)threadIdx.x : 0.0;
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   double *Dw = smem + HEAD + (long long)wave * lds_rows(NS, NET::R, LPC) * NS * 64;
