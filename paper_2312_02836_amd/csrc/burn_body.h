@@ -251,7 +251,7 @@ __device__ __forceinline__ void gargmax_key(double &v, int &key) {
 // LDS layout.  Per workgroup, the network tables (every array starts on a
 // 16-byte boundary, so a reaction's output list is one aligned 16-byte pair):
 //   rtab[8 Rb] (doubles, Rb = R rounded up to 32; see coef_of) | rout[8R] rsp[4R] (ints)
-//   | emult[R] q[R] qcv[R] (doubles)
+//   | emult[R] q[R] qcv[R] (doubles) | recip[8] (1/j for j = 0..7, entry 0 unused)
 // then one area per wave:
 //   D[CPW][DS] ybuf[CPW][YS] facc[CPW][YS] fslot[FC][FB] fsc[FC][4]
 // with FB = NP + n*MS + 2*NP + 1 doubles per factorization slot: y_J, the
@@ -268,7 +268,7 @@ __device__ __forceinline__ void gargmax_key(double &v, int &key) {
 // consecutive doubles (no bank conflicts), and the eight coefficients of a
 // reaction sit at constant offsets from its first.
 __host__ __device__ inline size_t rblk_of(int R) { return ((size_t)R + 31) & ~(size_t)31; }
-__host__ __device__ inline size_t tab_doubles_of(int R) { return 8 * rblk_of(R) + 9 * (size_t)R; }
+__host__ __device__ inline size_t tab_doubles_of(int R) { return 8 * rblk_of(R) + 9 * (size_t)R + 8; }
 
 // coefficient k of one reaction: c[k]
 struct Coef {
@@ -314,7 +314,7 @@ struct Shape {
 };
 
 struct Tabs {
-  const double *rtab, *emult, *q, *qcv;
+  const double *rtab, *emult, *q, *qcv, *recip;
   const int *rsp, *rout;
 };
 
@@ -354,6 +354,7 @@ __device__ __forceinline__ Tabs tabs_at(double *smem, int R) {
   t.emult = reinterpret_cast<const double *>(t.rsp + 4 * R);
   t.q = t.emult + R;
   t.qcv = t.q + R;
+  t.recip = t.qcv + R;
   return t;
 }
 
@@ -380,6 +381,9 @@ __device__ __forceinline__ void load_tables(const NetTables &nt, const double *l
     qcv[i] = nt.q[i] * nt.inv_cv;
   }
   for (int i = tid; i < 4 * R; i += nth) rsp[i] = nt.rsp[i];
+  // 1/j, correctly rounded (IEEE division): the step controller's
+  // order-dependent quotients read these instead of dividing
+  if (tid < 8) qcv[R + tid] = tid ? 1.0 / (double)tid : 0.0;
 }
 
 // Burn cells with one wave.  The cells come either from a static map (cell
@@ -451,6 +455,7 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
   }
 
   const double *s_rtab = tb.rtab, *s_emult = tb.emult, *s_q = tb.q, *s_qcv = tb.qcv;
+  const double *s_recip = tb.recip;
   const int *s_rsp = tb.rsp, *s_rout = tb.rout;
 
   // ---- per-lane state (group layout)
@@ -1167,8 +1172,13 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         // the slot's lanes (key: position, then the physical row, the payload;
         // positions of candidates are distinct, so the smallest key is the
         // first position).  Updates pos, fsing and fdinv; returns the pivot's
-        // physical row, and the row's entry K in mk.
-        auto pivot = [&](int K, double &mk) __attribute__((always_inline)) -> int {
+        // physical row, the row's entry K in mk and the pivot's reciprocal
+        // in rk.  With one slot per wave every candidate forms the reciprocal
+        // of its entry while the reduction runs and the pivot's is then read
+        // from its lane (the pivot is wave-uniform), so no division waits for
+        // the pivot to be known; narrower slots divide after the reduction
+        // (reading the pivot's lane per slot cost more than it saved).
+        auto pivot = [&](int K, double &mk, double &rk) __attribute__((always_inline)) -> int {
           double v = -2.0;
           int nan_k = 0;
           const bool cand = frow && pos >= K;
@@ -1181,8 +1191,13 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               v = -1.0;
             }
           }
+          const double rc = FL == 64 ? 1.0 / mk : 0.0;
           int key = cand ? ((pos << 8) | fi) : 0x7fffffff;
           gargmax_key<FL>(v, key);
+          if constexpr (FL == 64)
+            rk = readlane_f64(rc, __builtin_amdgcn_readfirstlane(key & 63));
+          else
+            rk = 1.0 / fM[(key & 255) * MS + K];
           const int bp = key >> 8;
           nan_k = gor<FL>(nan_k);
           if (!(v > 0.0) || nan_k) fsing = 1;
@@ -1201,9 +1216,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         // it, P2_j - l1' P1_j with that row's multiplier l1'): the trailing
         // entries are read and written once per two columns.
         for (int K = 0; K < n; K += 2) {
-          double mk;
-          const double *P1 = fM + pivot(K, mk) * MS;
-          const double rinv1 = 1.0 / P1[K];
+          double mk, rinv1;
+          const double *P1 = fM + pivot(K, mk, rinv1) * MS;
           if (frow && pos == K) fdinv = rinv1;
           const bool two = K + 1 < n;
           double l1 = 0.0;
@@ -1214,9 +1228,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
           }
           wave_lds_sync();
           if (!two) break;
-          double mk2;
-          const double *P2 = fM + pivot(K + 1, mk2) * MS;
-          const double rinv2 = 1.0 / P2[K + 1];
+          double mk2, rinv2;
+          const double *P2 = fM + pivot(K + 1, mk2, rinv2) * MS;
           const double l1p = P2[K];  // the multiplier of column K + 1's pivot row at column K
           if (frow && pos == K + 1) fdinv = rinv2;
           const bool below = frow && pos > K + 1;
@@ -1447,15 +1460,16 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         } else if (converged) {
           // error test, scale atol + rtol * max(|y_n|, |y_new|)
           double e1[S];
+          const double rk1 = s_recip[k + 1];
 #pragma unroll
           for (int s = 0; s < S; ++s) {
             const double aa = fabs(Dl[comp(s)]), bb = fabs(yv[s]);
             isc[s] = 1.0 / (atol + rtol * (aa > bb ? aa : bb));
-            e1[s] = dd[s] / (double)(k + 1);
+            e1[s] = bn_div_by(dd[s], (double)(k + 1), rk1);
           }
           err = wrms(e1, isc);
           if (err > 1.0) {
-            double fct = kSafety * exp(bn_log(err) * (-1.0 / (double)(k + 1)));
+            double fct = kSafety * exp(bn_log(err) * -rk1);
             if (fct < kMinFactor) fct = kMinFactor;
             h *= fct;
             pend = fct;
@@ -1484,8 +1498,8 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
                 }
               }
               if (i < n) {
-                const double zm = (Dl[k * NP + i] / (double)k) * isc[s];
-                const double zp = (dk2 / (double)(k + 2)) * isc[s];
+                const double zm = bn_div_by(Dl[k * NP + i], (double)k, s_recip[k]) * isc[s];
+                const double zp = bn_div_by(dk2, (double)(k + 2), s_recip[k + 2]) * isc[s];
                 em_acc += zm * zm;
                 ep_acc += zp * zp;
               }
@@ -1510,9 +1524,9 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
               const double ep = (k < KMAX) ? sqrt(bn_div_by(ep_acc, dn_sz, inv_n)) : INFINITY;
               // the factors norm^(-1/(order+1)) of orders k-1, k, k+1,
               // compared by their logarithms; one exponential for the best
-              const double lm = bn_log(em) * (-1.0 / (double)k);
-              const double l0 = bn_log(err) * (-1.0 / (double)(k + 1));
-              const double lp = bn_log(ep) * (-1.0 / (double)(k + 2));
+              const double lm = bn_log(em) * -s_recip[k];
+              const double l0 = bn_log(err) * -rk1;
+              const double lp = bn_log(ep) * -s_recip[k + 2];
               double best = l0;
               int dk = 0;
               if (lm > best) {
