@@ -624,26 +624,35 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     for (int s = 0; s < S; ++s) ybuf[comp(s)] = b[s];
     wave_lds_sync();
 #pragma unroll
-    for (int s = 0; s < S; ++s) b[s] = ybuf[ridx[s]];
+    for (int s = 0; s < S; ++s) {
+      b[s] = ybuf[ridx[s]];
+      if constexpr (SH::COMPACT) b[s] = comp(s) < n ? b[s] : 0.0;
+    }
     // forward substitution with the unit lower factor.  Positions K >= n
-    // are padding (zero right-hand side, zero factor columns, unit
-    // diagonal): with all NP rows stored they change nothing, so only the
-    // compact layout skips them.
-    // (n is made opaque before each sweep, so the column tests are not kept
+    // are padding (zero right-hand side, zero factor rows and columns, unit
+    // diagonal): they change nothing, so the compact layout skips the
+    // blocks of eight columns that lie wholly past n (one test per block;
+    // the padded columns of the last block run and add zeros).
+    // (n is made opaque before each sweep, so the block tests are not kept
     // from one sweep to the other)
+    constexpr int SB = NP < 8 ? NP : 8;  // columns per skip test
+    static_assert(NP % SB == 0, "whole blocks of columns");
     int nf = n;
     asm volatile("" : "+s"(nf));
-    Unroll<NP>::run([&]<int K>() __attribute__((always_inline)) {
-      if (!SH::COMPACT || K < nf) {
-        const double xk = gbcast<L, K % L>(b[K / L]);
-        // the factor column masked to the strictly lower part (a select
-        // that does not wait for xk) and an unconditional update: b - 0 xk
-        // is b
+    Unroll<NP / SB>::run([&]<int BK>() __attribute__((always_inline)) {
+      if (!SH::COMPACT || BK * SB < nf) {
+        Unroll<SB>::run([&]<int KI>() __attribute__((always_inline)) {
+          constexpr int K = BK * SB + KI;
+          const double xk = gbcast<L, K % L>(b[K / L]);
+          // the factor column masked to the strictly lower part (a select
+          // that does not wait for xk) and an unconditional update: b - 0 xk
+          // is b
 #pragma unroll
-        for (int s = K / L; s < S; ++s) {
-          const double lk = comp(s) > K ? LU[s][K] : 0.0;
-          b[s] = fma(-lk, xk, b[s]);
-        }
+          for (int s = K / L; s < S; ++s) {
+            const double lk = comp(s) > K ? LU[s][K] : 0.0;
+            b[s] = fma(-lk, xk, b[s]);
+          }
+        });
       }
     });
     // back substitution with the upper factor: at step K component K is
@@ -651,15 +660,18 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
     // scales its own components once at the end (the same product)
     int nb = n;
     asm volatile("" : "+s"(nb));
-    Unroll<NP>::run([&]<int KK>() __attribute__((always_inline)) {
-      constexpr int K = NP - 1 - KK;
-      if (!SH::COMPACT || K < nb) {
-        const double xk = gbcast<L, K % L>(b[K / L] * dinv[K / L]);
+    Unroll<NP / SB>::run([&]<int BB>() __attribute__((always_inline)) {
+      constexpr int BK = NP / SB - 1 - BB;
+      if (!SH::COMPACT || BK * SB < nb) {
+        Unroll<SB>::run([&]<int KI>() __attribute__((always_inline)) {
+          constexpr int K = BK * SB + SB - 1 - KI;
+          const double xk = gbcast<L, K % L>(b[K / L] * dinv[K / L]);
 #pragma unroll
-        for (int s = 0; s <= K / L; ++s) {
-          const double uk = comp(s) < K ? LU[s][K] : 0.0;  // strictly upper part
-          b[s] = fma(-uk, xk, b[s]);
-        }
+          for (int s = 0; s <= K / L; ++s) {
+            const double uk = comp(s) < K ? LU[s][K] : 0.0;  // strictly upper part
+            b[s] = fma(-uk, xk, b[s]);
+          }
+        });
       }
     });
 #pragma unroll
@@ -1288,14 +1300,15 @@ __device__ __forceinline__ void run_cells(const BurnArgs &a, const Tabs &tb, dou
         for (int s = 0; s < S; ++s) {
           const int p = comp(s);
           if (p < n) {
-            // entries j >= n of a row are never used by the solves; reading
-            // them stays inside this slot (the auxiliary rows follow)
+            // entries j >= n of a row (read inside this slot: the auxiliary
+            // rows follow) are replaced by zeros, which the padded columns
+            // of the solves' last block of columns multiply
             dinv[s] = saux[p];
             ridx[s] = (int)saux[NP + p];
             // register factorization: rows stored by position
             const double *row = src + (REG_LU ? p : ridx[s]) * MS;
 #pragma unroll
-            for (int j = 0; j < NP; ++j) LU[s][j] = row[j];
+            for (int j = 0; j < NP; ++j) LU[s][j] = (!SH::COMPACT || j < n) ? row[j] : 0.0;
           } else {
             dinv[s] = 1.0;
             ridx[s] = p;
